@@ -1,0 +1,176 @@
+"""Oracle for the rank-profile-revealing PLUQ over GF(p).
+
+TEST INFRASTRUCTURE: a plain CPU reference (C, see pluqz_oracle.c) that the
+tests, the smoke entry point and the benchmark's CPU-baseline leg compare the
+GPU library against.  Nothing in the library imports this package.
+
+Stages (paper: Dumas, Pernet, Sultan, ISSAC 2013):
+  rpm()         S1, rank profile matrix by Algorithm 2 (Section 7), corrected;
+  zorder()      S2, pivot order of Algorithm 1 (Section 2) from the RPM;
+  ordered_lu()  S3, elimination without pivoting of A[P, Q];
+  pluqz()       S1+S2+S3.
+Also the Section 2 building blocks mm(), trsm_llu(), trsm_run() and the
+field helpers inv(), mulmod().
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        u64, i64 = ctypes.c_uint64, ctypes.c_int64
+        L.oracle_inv.restype = u64
+        L.oracle_inv.argtypes = [u64, u64]
+        L.oracle_mulmod.restype = u64
+        L.oracle_mulmod.argtypes = [u64, u64, u64]
+        L.oracle_rpm.restype = i64
+        L.oracle_rpm.argtypes = [i64, i64, _i64p, u64, _i64p]
+        L.oracle_zorder.restype = i64
+        L.oracle_zorder.argtypes = [i64, i64, _i64p, _i64p, _i64p]
+        L.oracle_ordered_lu.restype = ctypes.c_int
+        L.oracle_ordered_lu.argtypes = [i64, i64, _i64p, u64, i64, _i64p, _i64p, _i64p]
+        L.oracle_pluqz.restype = ctypes.c_int
+        L.oracle_pluqz.argtypes = [i64, i64, _i64p, u64, _i64p, _i64p, _i64p, _i64p]
+        L.oracle_mm.restype = None
+        L.oracle_mm.argtypes = [i64, i64, i64, _i64p, i64, _i64p, i64, _i64p, i64, u64]
+        L.oracle_trsm_llu.restype = None
+        L.oracle_trsm_llu.argtypes = [i64, i64, _i64p, i64, _i64p, i64, u64]
+        L.oracle_trsm_run.restype = None
+        L.oracle_trsm_run.argtypes = [i64, i64, _i64p, i64, _i64p, i64, u64]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_i64p)
+
+
+def _mat(A) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(A, dtype=np.int64))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def inv(a: int, p: int) -> int:
+    return int(lib().oracle_inv(int(a) % p, p))
+
+
+def mulmod(a: int, b: int, p: int) -> int:
+    return int(lib().oracle_mulmod(int(a), int(b), p))
+
+
+def rpm(A, p: int):
+    """S1: returns (r, rpm_col) with rpm_col[i] = pivot column of row i or -1."""
+    W = _mat(A).copy()
+    m, n = W.shape
+    rc = np.full(max(m, 1), -1, dtype=np.int64)
+    r = lib().oracle_rpm(m, n, _p(W), p, _p(rc))
+    if r < 0:
+        raise OracleError("oracle_rpm: out of memory")
+    return int(r), rc[:m]
+
+
+def rpm_pairs(A, p: int) -> np.ndarray:
+    """Sorted (row, col) pairs of the rank profile matrix."""
+    _, rc = rpm(A, p)
+    rows = np.nonzero(rc >= 0)[0]
+    return np.stack([rows, rc[rows]], axis=1).astype(np.int64) if len(rows) else np.zeros((0, 2), np.int64)
+
+
+def zorder(m: int, n: int, rpm_col):
+    """S2: (r, P, Q) from an RPM given as rpm_col (length m, -1 = no pivot)."""
+    rc = np.ascontiguousarray(np.asarray(rpm_col, dtype=np.int64))
+    P = np.zeros(max(m, 1), np.int64)
+    Q = np.zeros(max(n, 1), np.int64)
+    r = lib().oracle_zorder(m, n, _p(rc), _p(P), _p(Q))
+    if r < 0:
+        raise OracleError("oracle_zorder: out of memory")
+    return int(r), P[:m], Q[:n]
+
+
+def ordered_lu(A, p: int, r: int, P, Q) -> np.ndarray:
+    """S3: packed no-pivot LU of A[P, Q]."""
+    A = _mat(A)
+    m, n = A.shape
+    X = np.zeros((m, n), np.int64)
+    P = np.ascontiguousarray(P, dtype=np.int64)
+    Q = np.ascontiguousarray(Q, dtype=np.int64)
+    rc = lib().oracle_ordered_lu(m, n, _p(A), p, r, _p(P), _p(Q), _p(X))
+    if rc != 0:
+        raise OracleError(f"oracle_ordered_lu self-check failed (code {rc})")
+    return X
+
+
+def pluqz(A, p: int):
+    """Full oracle: returns (P, Q, r, X) with X the packed [L\\U V; M 0]."""
+    A = _mat(A)
+    m, n = A.shape
+    P = np.zeros(max(m, 1), np.int64)
+    Q = np.zeros(max(n, 1), np.int64)
+    X = np.zeros((m, n), np.int64) if m * n else np.zeros((m, n), np.int64)
+    r = ctypes.c_int64(0)
+    rc = lib().oracle_pluqz(m, n, _p(A) if m * n else None, p, _p(P), _p(Q),
+                            _p(X) if m * n else None, ctypes.byref(r))
+    if rc != 0:
+        raise OracleError(f"oracle_pluqz failed (code {rc})")
+    return P[:m], Q[:n], int(r.value), X
+
+
+def mm(C, A, B, p: int) -> np.ndarray:
+    """MM(C, A, B): returns C - A.B mod p (inputs untouched)."""
+    C = _mat(C).copy()
+    A = _mat(A)
+    B = _mat(B)
+    m, n = C.shape
+    k = A.shape[1]
+    lib().oracle_mm(m, n, k, _p(C), n, _p(A), k, _p(B), n, p)
+    return C
+
+
+def trsm_llu(L, B, p: int) -> np.ndarray:
+    """L^{-1} B with L unit lower triangular (diagonal ignored)."""
+    L = _mat(L)
+    B = _mat(B).copy()
+    r, n = B.shape
+    lib().oracle_trsm_llu(r, n, _p(L), L.shape[1], _p(B), n, p)
+    return B
+
+
+def trsm_run(B, U, p: int) -> np.ndarray:
+    """B U^{-1} with U upper triangular, non-zero diagonal."""
+    U = _mat(U)
+    B = _mat(B).copy()
+    m, r = B.shape
+    lib().oracle_trsm_run(m, r, _p(B), r, _p(U), U.shape[1], p)
+    return B
+
+
+def rank_profiles(P, Q, r: int):
+    """Row and column rank profiles: sorted first r entries of P and Q
+    (corollary at the end of Section 4)."""
+    return np.sort(np.asarray(P[:r])), np.sort(np.asarray(Q[:r]))
+
+
+def leading_rank_profiles(P, Q, r: int, k: int, t: int):
+    """Rank profiles of the leading k x t sub-matrix: rows / columns of the
+    non-zero entries of the leading k x t block of P [I_r 0; 0 0] Q
+    (corollary of Section 4).  Returns (rows, cols), both sorted."""
+    P = np.asarray(P)
+    Q = np.asarray(Q)
+    sel = (P[:r] < k) & (Q[:r] < t)
+    return np.sort(P[:r][sel]), np.sort(Q[:r][sel])
