@@ -1,0 +1,150 @@
+"""Benchmark of the rank-profile PLUQ on one MI355X.
+
+A step is one whole decomposition of each matrix of the workload (restored
+from a pristine device copy first, since the decomposition is in place).
+Default workload: 4096 x 4096 over GF(65521), two matrices per step -- a
+full-rank uniform one and a rank-2048 permuted X.Y product -- in the FP64
+matrix-core form with float64 storage.
+
+Metric: effective GOPS = sum over the step's matrices of 2 m n r, divided by
+the wall time of the timed steps.  Also reported: the classical-operation
+rate (2 * sum_{k<r} (m-k-1)(n-k-1) per matrix), the roofline position of the
+dominant kernel (the MM update, timed with HIP events on the library's
+stream inside the timed region), and the CPU oracle on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "effective GOPS (2mnr) of PLUQ mod p, INT8-limb & batched vs plain FP64"
+FP64_MFMA_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def classical_ops(m: int, n: int, r: int) -> float:
+    """2 * sum_{k<r} (m-k-1)(n-k-1): multiply-adds of Gaussian elimination, x2."""
+    s = 0
+    for k in range(r):
+        s += (m - k - 1) * (n - k - 1)
+    return 2.0 * s
+
+
+def make_workload(name: str, seed: int):
+    import torch
+    import pluq_inputs as gen
+    if name == "c2":
+        p, n = 65521, 4096
+        full = torch.from_numpy(gen.uniform(n, n, p, seed)).to(torch.float64).cuda()
+        half = gen.xy_permuted(n, n, 2048, p, seed, device="cuda").to(torch.float64)
+        desc = ("4096x4096 over GF(65521): full-rank uniform + rank-2048 permuted X.Y, "
+                "two matrices per step, FP64 matrix-core form, float64 storage")
+        return p, [full, half], desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(seed: int):
+    """The oracle on the same recipe at half size (2048 x 2048: full-rank
+    uniform + rank-1024 permuted X.Y), scaled to effective GOPS."""
+    import oracle
+    import pluq_inputs as gen
+    p, n = 65521, 2048
+    mats = [gen.uniform(n, n, p, seed), gen.xy_permuted(n, n, n // 2, p, seed)]
+    ops = 0.0
+    t0 = time.perf_counter()
+    for A in mats:
+        _, _, r, _ = oracle.pluqz(A, p)
+        ops += 2.0 * n * n * r
+    dt = time.perf_counter() - t0
+    return {"value": ops / dt / 1e9, "unit": "GOPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"2048x2048 over GF({p}): full-rank uniform + rank-1024 permuted X.Y "
+                      f"(same recipe at half size), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1301_4438_amd as pl
+    pl.load()
+    p, pristine, desc = make_workload(args.workload, args.seed)
+    work = [a.clone() for a in pristine]
+    Ps = [torch.empty(a.shape[0], dtype=torch.int64, device="cuda") for a in pristine]
+    Qs = [torch.empty(a.shape[1], dtype=torch.int64, device="cuda") for a in pristine]
+    opts = pl._opts("fp64")
+
+    def step():
+        rs = []
+        for i in range(len(work)):
+            work[i].copy_(pristine[i])
+            rs.append(pl.pluq_modp(work[i], p, Ps[i], Qs[i], opts))
+        return rs
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    pl.pluq_profile_enable(1 << 0)          # time the MM updates only
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ranks = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = pl.pluq_profile_read()
+    pl.pluq_profile_enable(0)
+    stats = pl.pluq_last_stats()
+
+    secs = t1 - t0
+    eff_ops = sum(2.0 * a.shape[0] * a.shape[1] * r for a, r in zip(pristine, ranks)) * args.steps
+    cls_ops = sum(classical_ops(a.shape[0], a.shape[1], r) for a, r in zip(pristine, ranks)) * args.steps
+    mm = prof["modmm"]
+    achieved = mm["flops"] / (mm["ms"] * 1e-3) / 1e12 if mm["ms"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": eff_ops / secs / 1e9,
+        "unit": "GOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "m": pristine[0].shape[0], "n": pristine[0].shape[1], "p": p,
+                   "ranks": ranks, "form": "fp64", "storage": "float64"},
+        "classical_gops": cls_ops / secs / 1e9,
+        "roofline": {"bound": "mfma", "kernel": "modmm_f64", "achieved": achieved,
+                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                     "launches": mm["launches"], "avg_launch_ms": mm["ms"] / max(mm["launches"], 1),
+                     "mm_share_of_step": (mm["ms"] * 1e-3) / secs,
+                     "traffic": None},
+        "library_stats_last_call": stats,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

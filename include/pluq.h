@@ -1,0 +1,231 @@
+/*
+ * pluq.h -- C ABI of the MI355X (gfx950) rank-profile-revealing PLUQ library.
+ *
+ * The library computes the PLUQ decomposition of Dumas, Pernet and Sultan,
+ * "Simultaneous computation of the row and column rank profiles" (ISSAC 2013),
+ * of an m x n matrix A of rank r over a prime field GF(p):
+ *
+ *     A = P [L; M] [U V] Q                      (Algorithm 1, Section 2)
+ *
+ * with L r x r unit lower triangular, U r x r upper triangular, and A
+ * overwritten in place by the packed form [L\U V; M 0].  P and Q come from
+ * the quad-recursive pivoting of Algorithm 1: the first r entries of P (of Q)
+ * are the pivot rows (columns), so the row and column rank profiles of A and
+ * of every leading k x t sub-matrix are read off P and Q (corollaries of
+ * Section 4).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ *  - Storage is row-major: element (i, j) is at A[i * lda + j], lda >= n.
+ *  - Entries are canonical integers in [0, p), stored exactly in the chosen
+ *    element type (int64, float64 or int32).  On return A again holds
+ *    canonical values.
+ *  - Permutation vectors are int64: P[i] is the original row of packed row i
+ *    and Q[j] the original column of packed column j, so that
+ *    A_in[P[i], Q[j]] == (L U)[i, j] for every i, j.
+ *  - The result is unique: pivots in the order of Algorithm 1's four
+ *    recursive calls with floor(m/2) x floor(n/2) splits, the non-pivot rows
+ *    and columns after them in ascending order, and [L\U V; M 0] the LU
+ *    factorisation without pivoting of A_in[P, Q].  No option changes it.
+ *  - Supported moduli: p prime, 2 <= p < 2^26 (every product of two reduced
+ *    residues is then exact in an IEEE double).  Primality is not checked.
+ *  - Device pointers are HIP device allocations of the calling process; host
+ *    pointers are ordinary host memory.  The caller owns every buffer.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All device work
+ *    is issued on it.  Calls returning a host-visible result (r) synchronise
+ *    the stream before returning.
+ *  - Functions never throw; they return a pluq_status.  Arguments are
+ *    validated before any device memory is touched.  PLUQ_ERR_DEVICE means a
+ *    HIP call failed after work started: the contents of A, P and Q are then
+ *    unspecified.
+ *  - Calls are not re-entrant on the same buffers; distinct calls on distinct
+ *    buffers and streams may run concurrently.
+ */
+#ifndef PLUQ_H
+#define PLUQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PLUQ_OK = 0,
+    PLUQ_ERR_ARG = 1,          /* bad dimension, leading dimension, null pointer */
+    PLUQ_ERR_MODULUS = 2,      /* p outside [2, 2^26) */
+    PLUQ_ERR_RANGE = 3,        /* an entry outside [0, p) (only with validation) */
+    PLUQ_ERR_UNSUPPORTED = 4,  /* the requested form cannot be exact for this p */
+    PLUQ_ERR_NOMEM = 5,        /* host allocation failed */
+    PLUQ_ERR_DEVICE = 6,       /* a HIP call failed */
+    PLUQ_ERR_WORKSPACE = 7     /* workspace smaller than pluq_workspace_size() */
+} pluq_status;
+
+/* Element storage type of the matrices passed in. */
+typedef enum { PLUQ_I64 = 0, PLUQ_F64 = 1, PLUQ_I32 = 2 } pluq_dtype;
+
+/* Arithmetic form of the matrix-multiply updates (the other steps are the
+ * same in every form).  All forms give bit-identical results.
+ *   FP64 -- float64 matrix cores, residues in symmetric form, products
+ *           accumulated exactly and reduced once per chunk of the inner
+ *           dimension (delayed reduction, Section 6): needs a chunk K >= 16
+ *           with K * ((p-1)/2)^2 + 4p < 2^52, i.e. p < 2^26.
+ *   INT8 -- residues split into signed 8-bit limbs on int8 matrix cores with
+ *           int32 accumulation, recombined exactly in float64 (p <= 65521,
+ *           one limb for p <= 251).
+ *   FP32 -- float32 matrix cores on symmetric residues for p < 2^11, with the
+ *           inner dimension chunked so every partial sum is below 2^24.
+ */
+typedef enum { PLUQ_FORM_FP64 = 0, PLUQ_FORM_INT8 = 1, PLUQ_FORM_FP32 = 2 } pluq_form;
+
+typedef struct {
+    int32_t form;             /* pluq_form */
+    int32_t validate_entries; /* non-zero: scan A for entries outside [0,p) first */
+    int32_t cutoff_override;  /* > 0: base-case capacity in elements (tuning only) */
+    int32_t trsm_leaf_override; /* > 0: order of the TRSM leaf solves, <= 64 (tuning only) */
+} pluq_opts;
+
+/* Human-readable name of a status code (static storage). */
+const char *pluq_status_string(pluq_status s);
+
+/* Library version string (static storage). */
+const char *pluq_version(void);
+
+/*
+ * Device workspace, in bytes, needed by pluq_modp for an m x n matrix of the
+ * given element type, modulus and options (opts may be NULL for defaults).
+ * Returns 0 for invalid arguments.
+ */
+size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p,
+                           const pluq_opts *opts);
+
+/*
+ * PLUQ decomposition, Algorithm 1 (Section 2), of the m x n matrix at dA.
+ *   dA       device, m x n row-major, leading dimension lda >= max(1, n);
+ *            overwritten by [L\U V; M 0] (canonical residues).
+ *   dP, dQ   device int64 arrays of length m and n (may be NULL when m or n
+ *            is 0); receive P and Q as described above.
+ *   r_out    host; receives the rank r.
+ *   opts     NULL for defaults (FP64 form, no validation).
+ *   dWork    device workspace of work_bytes >= pluq_workspace_size(...),
+ *            256-byte aligned; its contents are scratch.
+ * m == 0 or n == 0 gives r = 0 and identity permutations.
+ * Errors: PLUQ_ERR_ARG, PLUQ_ERR_MODULUS, PLUQ_ERR_UNSUPPORTED,
+ * PLUQ_ERR_WORKSPACE (all before A is touched), PLUQ_ERR_RANGE (validation
+ * scan, A untouched), PLUQ_ERR_DEVICE.
+ */
+pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt,
+                      uint64_t p, int64_t *dP, int64_t *dQ, int64_t *r_out,
+                      const pluq_opts *opts, void *dWork, size_t work_bytes,
+                      void *stream);
+
+/*
+ * Row and column rank profiles from P, Q and r (host arrays): the sorted
+ * first r entries of P and of Q (last corollary of Section 4).
+ * row_rp and col_rp receive r values each.
+ */
+pluq_status pluq_rank_profiles(int64_t m, int64_t n, int64_t r, const int64_t *P,
+                               const int64_t *Q, int64_t *row_rp, int64_t *col_rp);
+
+/*
+ * Rank profiles of the leading k x t sub-matrix of A (first corollary of
+ * Section 4): the sorted row and column indices of the non-zero entries of
+ * the leading k x t block of P [I_r 0; 0 0] Q, i.e. the pivots (P[s], Q[s]),
+ * s < r, with P[s] < k and Q[s] < t.  rows and cols (host, capacity >= r)
+ * receive `*count` sorted indices each.
+ */
+pluq_status pluq_leading_rank_profiles(int64_t m, int64_t n, int64_t r,
+                                       const int64_t *P, const int64_t *Q,
+                                       int64_t k, int64_t t, int64_t *rows,
+                                       int64_t *cols, int64_t *count);
+
+/*
+ * Batched PLUQ: `batch` independent matrices, each processed as by
+ * pluq_modp, in one persistent launch on `stream`.
+ *   m, n, lda        host arrays of length batch.
+ *   dA, dP, dQ       host arrays of `batch` device pointers.
+ *   d_r              device int64 array of length batch; receives the ranks.
+ *   dWork/work_bytes device workspace >= pluq_batched_workspace_size(...).
+ * The call does not synchronise the stream; d_r is valid once the stream
+ * reaches it.  Errors as for pluq_modp.
+ */
+size_t pluq_batched_workspace_size(int64_t batch, const int64_t *m, const int64_t *n,
+                                   pluq_dtype dt, uint64_t p, const pluq_opts *opts);
+pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n,
+                              void *const *dA, const int64_t *lda, pluq_dtype dt,
+                              uint64_t p, int64_t *const *dP, int64_t *const *dQ,
+                              int64_t *d_r, const pluq_opts *opts, void *dWork,
+                              size_t work_bytes, void *stream);
+
+/* ---- building blocks of Section 2 (device, for direct use and tests) ---- */
+
+/*
+ * MM(C, A, B) of Section 2: C <- C - A B mod p, with C m x n (ldc), A m x k
+ * (lda), B k x n (ldb), all device, row-major, element type dt, canonical
+ * residues.  `form` selects the matrix-core arithmetic (pluq_form); results
+ * are identical for every form.  dWork/work_bytes: scratch for the INT8
+ * form's limb planes (>= pluq_modmm_workspace_size; may be NULL otherwise).
+ * Asynchronous on `stream`.
+ */
+size_t pluq_modmm_workspace_size(int64_t m, int64_t n, int64_t k, int32_t form);
+pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
+                       const void *dA, int64_t lda, const void *dB, int64_t ldb,
+                       pluq_dtype dt, uint64_t p, int32_t form, void *dWork,
+                       size_t work_bytes, void *stream);
+
+/*
+ * TRSM of Section 2 (device, row-major, canonical residues, asynchronous):
+ *   side = 0: B <- L^{-1} B, L r x r unit lower triangular (its diagonal and
+ *             upper part are not read), B r x ncols;
+ *   side = 1: B <- B U^{-1}, U r x r upper triangular with non-zero diagonal
+ *             (its strict lower part is not read), B nrows x r.
+ * `other` is ncols (side 0) or nrows (side 1).
+ */
+pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT,
+                      int64_t ldt, void *dB, int64_t ldb, pluq_dtype dt, uint64_t p,
+                      int32_t form, void *dWork, size_t work_bytes, void *stream);
+
+/*
+ * Statistics of the last pluq_modp call on this thread (host): number of
+ * recursion nodes, base cases, kernel launches and stream synchronisations.
+ * Any pointer may be NULL.
+ */
+void pluq_last_stats(int64_t *nodes, int64_t *basecases, int64_t *launches,
+                     int64_t *syncs);
+
+/*
+ * Per-kernel-class timing (host, per calling thread).  When enabled, every
+ * kernel launch of pluq_modp is bracketed by HIP events on the caller's
+ * stream and, per class, the launch count, the summed device time and the
+ * algorithmic work are accumulated:
+ *   flops -- 2 * M * N * K of each matrix-multiply update (the classical
+ *            multiply-add count), 0 for the other classes;
+ *   bytes -- compulsory HBM traffic of the launch (operands read once,
+ *            outputs read and written once).
+ * pluq_profile_enable(mask) resets the counters and records the classes
+ * whose bit (1 << class) is set in mask (-1: all, 0: stop); untimed classes
+ * cost nothing.  pluq_profile_read fills PLUQ_K_COUNT entries.
+ */
+enum {
+    PLUQ_K_MODMM = 0,     /* MM updates (Schur complements, TRSM updates) */
+    PLUQ_K_TRSM_LEAF = 1, /* triangular-solve leaves */
+    PLUQ_K_PERM = 2,      /* row / column permutations */
+    PLUQ_K_BASECASE = 3,  /* base-case tiles */
+    PLUQ_K_SCAN = 4,      /* zero / range scans */
+    PLUQ_K_COUNT = 5
+};
+typedef struct {
+    int64_t launches;
+    double ms;
+    double flops;
+    double bytes;
+} pluq_kernel_stat;
+void pluq_profile_enable(int32_t mask);
+void pluq_profile_read(pluq_kernel_stat *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLUQ_H */

@@ -34,6 +34,8 @@ def lib():
         u64, i64 = ctypes.c_uint64, ctypes.c_int64
         L.oracle_inv.restype = u64
         L.oracle_inv.argtypes = [u64, u64]
+        L.oracle_threads.restype = ctypes.c_int
+        L.oracle_threads.argtypes = []
         L.oracle_mulmod.restype = u64
         L.oracle_mulmod.argtypes = [u64, u64, u64]
         L.oracle_rpm.restype = i64
@@ -64,6 +66,11 @@ def _mat(A) -> np.ndarray:
 
 class OracleError(RuntimeError):
     pass
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's parallel loops."""
+    return int(lib().oracle_threads())
 
 
 def inv(a: int, p: int) -> int:

@@ -35,6 +35,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_ERR_ARG 1
@@ -62,6 +65,16 @@ uint64_t oracle_inv(uint64_t a, uint64_t p)
     if (r != 1) return 0; /* not invertible */
     if (t < 0) t += (int64_t)p;
     return (uint64_t)t;
+}
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 uint64_t oracle_mulmod(uint64_t a, uint64_t b, uint64_t p) { return fmul(a, b, p); }

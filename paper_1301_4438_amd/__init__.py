@@ -1,0 +1,271 @@
+"""Python binding of libpluq.so, the MI355X rank-profile PLUQ library.
+
+Argument marshalling only: every step of the decomposition runs in the HIP
+library.  PyTorch provides device memory and the current stream.  The
+functions carry the names of the C ABI in include/pluq.h; ``pluq`` is a
+convenience wrapper that allocates P, Q and the workspace.
+
+There is no fallback: if libpluq.so is missing or a call fails, an exception
+is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpluq.so")
+
+PLUQ_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "modulus outside [2, 2^26)", 3: "entry outside [0, p)",
+          4: "form cannot be exact for this modulus", 5: "host allocation failed",
+          6: "device (HIP) error", 7: "workspace too small"}
+DTYPES = {"int64": 0, "float64": 1, "int32": 2}
+FORMS = {"fp64": 0, "int8": 1, "fp32": 2}
+
+_lib = None
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_vp = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+class PluqError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class pluq_opts(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("validate_entries", ctypes.c_int32),
+                ("cutoff_override", ctypes.c_int32), ("trsm_leaf_override", ctypes.c_int32)]
+
+
+class pluq_kernel_stat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("flops", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
+KERNEL_CLASSES = ["modmm", "trsm_leaf", "perm", "basecase", "scan"]
+
+
+def load():
+    """Load libpluq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1301_4438_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    L.pluq_status_string.restype = ctypes.c_char_p
+    L.pluq_status_string.argtypes = [ctypes.c_int]
+    L.pluq_version.restype = ctypes.c_char_p
+    L.pluq_workspace_size.restype = ctypes.c_size_t
+    L.pluq_workspace_size.argtypes = [_i64, _i64, ctypes.c_int, _u64, ctypes.POINTER(pluq_opts)]
+    L.pluq_modp.restype = ctypes.c_int
+    L.pluq_modp.argtypes = [_i64, _i64, _vp, _i64, ctypes.c_int, _u64, _vp, _vp, _i64p,
+                            ctypes.POINTER(pluq_opts), _vp, ctypes.c_size_t, _vp]
+    L.pluq_rank_profiles.restype = ctypes.c_int
+    L.pluq_rank_profiles.argtypes = [_i64, _i64, _i64, _i64p, _i64p, _i64p, _i64p]
+    L.pluq_leading_rank_profiles.restype = ctypes.c_int
+    L.pluq_leading_rank_profiles.argtypes = [_i64, _i64, _i64, _i64p, _i64p, _i64, _i64, _i64p, _i64p, _i64p]
+    L.pluq_batched_workspace_size.restype = ctypes.c_size_t
+    L.pluq_batched_workspace_size.argtypes = [_i64, _i64p, _i64p, ctypes.c_int, _u64, ctypes.POINTER(pluq_opts)]
+    L.pluq_modp_batched.restype = ctypes.c_int
+    L.pluq_modp_batched.argtypes = [_i64, _i64p, _i64p, ctypes.POINTER(_vp), _i64p, ctypes.c_int, _u64,
+                                    ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(pluq_opts),
+                                    _vp, ctypes.c_size_t, _vp]
+    L.pluq_modmm_workspace_size.restype = ctypes.c_size_t
+    L.pluq_modmm_workspace_size.argtypes = [_i64, _i64, _i64, ctypes.c_int32]
+    L.pluq_modmm.restype = ctypes.c_int
+    L.pluq_modmm.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
+                             ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    L.pluq_trsm.restype = ctypes.c_int
+    L.pluq_trsm.argtypes = [ctypes.c_int32, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
+                            ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    L.pluq_profile_enable.restype = None
+    L.pluq_profile_enable.argtypes = [ctypes.c_int32]
+    L.pluq_profile_read.restype = None
+    L.pluq_profile_read.argtypes = [ctypes.POINTER(pluq_kernel_stat)]
+    L.pluq_last_stats.restype = None
+    L.pluq_last_stats.argtypes = [_i64p, _i64p, _i64p, _i64p]
+    _lib = L
+    return L
+
+
+# --------------------------------------------------------------- helpers --
+
+def _dtype_code(t) -> int:
+    import torch
+    m = {torch.int64: 0, torch.float64: 1, torch.int32: 2}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported element type {t.dtype} (int64, float64 or int32)")
+    return m[t.dtype]
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _opts(form="fp64", validate=False, cutoff=0, trsm_leaf=0):
+    o = pluq_opts()
+    o.form = FORMS[form] if isinstance(form, str) else int(form)
+    o.validate_entries = int(bool(validate))
+    o.cutoff_override = int(cutoff)
+    o.trsm_leaf_override = int(trsm_leaf)
+    return o
+
+
+def _check(st, where):
+    if st != PLUQ_OK:
+        raise PluqError(st, where)
+
+
+_ws_cache = {}
+
+
+def _workspace(device, nbytes):
+    import torch
+    key = str(device)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+# ------------------------------------------------------------ C ABI names --
+
+def pluq_status_string(status: int) -> str:
+    return load().pluq_status_string(int(status)).decode()
+
+
+def pluq_version() -> str:
+    return load().pluq_version().decode()
+
+
+def pluq_workspace_size(m, n, dtype_code, p, opts=None) -> int:
+    return int(load().pluq_workspace_size(m, n, dtype_code, p, ctypes.byref(opts) if opts else None))
+
+
+def pluq_modp(A, p: int, P, Q, opts=None, work=None):
+    """In-place decomposition of the 2-D device tensor A (row-major, any
+    leading dimension).  P, Q: device int64 tensors of length m, n.
+    Returns r."""
+    L = load()
+    m, n = A.shape
+    lda = A.stride(0) if m > 0 else max(1, n)
+    if A.dim() != 2 or (m > 0 and n > 1 and A.stride(1) != 1):
+        raise ValueError("A must be a row-major 2-D tensor with unit column stride")
+    if m == 0 or n == 0:
+        lda = max(1, n)
+    dt = _dtype_code(A)
+    need = L.pluq_workspace_size(m, n, dt, p, ctypes.byref(opts) if opts else None)
+    if work is None:
+        work = _workspace(A.device, need)
+    r = ctypes.c_int64(0)
+    st = L.pluq_modp(m, n, ctypes.c_void_p(A.data_ptr()), max(lda, 1), dt, p,
+                     ctypes.c_void_p(P.data_ptr() if m else 0), ctypes.c_void_p(Q.data_ptr() if n else 0),
+                     ctypes.byref(r), ctypes.byref(opts) if opts else None,
+                     ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(A))
+    _check(st, "pluq_modp")
+    return int(r.value)
+
+
+def pluq_rank_profiles(P, Q, r):
+    """Host arrays (numpy/torch CPU int64) -> (row_rp, col_rp) numpy arrays."""
+    import numpy as np
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.int64))
+    Q = np.ascontiguousarray(np.asarray(Q, dtype=np.int64))
+    rr = np.zeros(max(r, 1), np.int64)
+    cc = np.zeros(max(r, 1), np.int64)
+    st = load().pluq_rank_profiles(len(P), len(Q), r, P.ctypes.data_as(_i64p), Q.ctypes.data_as(_i64p),
+                                   rr.ctypes.data_as(_i64p), cc.ctypes.data_as(_i64p))
+    _check(st, "pluq_rank_profiles")
+    return rr[:r], cc[:r]
+
+
+def pluq_leading_rank_profiles(P, Q, r, k, t):
+    import numpy as np
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.int64))
+    Q = np.ascontiguousarray(np.asarray(Q, dtype=np.int64))
+    rows = np.zeros(max(r, 1), np.int64)
+    cols = np.zeros(max(r, 1), np.int64)
+    cnt = ctypes.c_int64(0)
+    st = load().pluq_leading_rank_profiles(len(P), len(Q), r, P.ctypes.data_as(_i64p), Q.ctypes.data_as(_i64p),
+                                           k, t, rows.ctypes.data_as(_i64p), cols.ctypes.data_as(_i64p),
+                                           ctypes.byref(cnt))
+    _check(st, "pluq_leading_rank_profiles")
+    return rows[:cnt.value], cols[:cnt.value]
+
+
+def pluq_modmm(C, A, B, p: int, form="fp64", work=None):
+    """C <- C - A B mod p on device tensors (in place, asynchronous)."""
+    L = load()
+    m, n = C.shape
+    k = A.shape[1]
+    if tuple(A.shape) != (m, k) or tuple(B.shape) != (k, n):
+        raise ValueError(f"shape mismatch: C {tuple(C.shape)}, A {tuple(A.shape)}, B {tuple(B.shape)}")
+    if A.dtype != C.dtype or B.dtype != C.dtype:
+        raise TypeError("A, B and C must share one element type")
+    for t in (A, B, C):
+        if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+            raise ValueError("operands must be row-major 2-D tensors with unit column stride")
+    dt = _dtype_code(C)
+    fcode = FORMS[form] if isinstance(form, str) else int(form)
+    need = int(L.pluq_modmm_workspace_size(m, n, k, fcode))
+    if work is None and need:
+        work = _workspace(C.device, need)
+    st = L.pluq_modmm(m, n, k, ctypes.c_void_p(C.data_ptr()), C.stride(0), ctypes.c_void_p(A.data_ptr()),
+                      A.stride(0), ctypes.c_void_p(B.data_ptr()), B.stride(0), dt, p, fcode,
+                      ctypes.c_void_p(work.data_ptr() if work is not None else 0),
+                      work.numel() if work is not None else 0, _stream(C))
+    _check(st, "pluq_modmm")
+
+
+def pluq_trsm(side: int, T, B, p: int, form="fp64"):
+    """side 0: B <- L^{-1} B (L unit lower, r x r); side 1: B <- B U^{-1}."""
+    L = load()
+    r = T.shape[0]
+    other = B.shape[1] if side == 0 else B.shape[0]
+    if tuple(T.shape) != (r, r) or (B.shape[0] if side == 0 else B.shape[1]) != r:
+        raise ValueError(f"shape mismatch: T {tuple(T.shape)}, B {tuple(B.shape)}, side {side}")
+    if T.dtype != B.dtype:
+        raise TypeError("T and B must share one element type")
+    dt = _dtype_code(B)
+    fcode = FORMS[form] if isinstance(form, str) else int(form)
+    st = L.pluq_trsm(side, r, other, ctypes.c_void_p(T.data_ptr()), T.stride(0), ctypes.c_void_p(B.data_ptr()),
+                     B.stride(0), dt, p, fcode, None, 0, _stream(B))
+    _check(st, "pluq_trsm")
+
+
+def pluq_profile_enable(mask=-1):
+    """mask: bit c times kernel class c (KERNEL_CLASSES order); -1 all, 0 off."""
+    load().pluq_profile_enable(int(mask))
+
+
+def pluq_profile_read():
+    arr = (pluq_kernel_stat * len(KERNEL_CLASSES))()
+    load().pluq_profile_read(arr)
+    return {name: {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops, "bytes": arr[i].bytes}
+            for i, name in enumerate(KERNEL_CLASSES)}
+
+
+def pluq_last_stats():
+    a, b, c, d = (ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64())
+    load().pluq_last_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d))
+    return {"nodes": a.value, "basecases": b.value, "launches": c.value, "syncs": d.value}
+
+
+# ------------------------------------------------------------ convenience --
+
+def pluq(A, p: int, form="fp64", validate=False, cutoff=0, trsm_leaf=0):
+    """Decompose the device tensor A in place.  Returns (P, Q, r) with P, Q
+    device int64 tensors."""
+    import torch
+    m, n = A.shape
+    P = torch.empty(m, dtype=torch.int64, device=A.device)
+    Q = torch.empty(n, dtype=torch.int64, device=A.device)
+    r = pluq_modp(A, p, P, Q, _opts(form, validate, cutoff, trsm_leaf))
+    return P, Q, r

@@ -1,0 +1,409 @@
+// extern "C" entry points (declared in include/pluq.h): argument checks,
+// workspace carving, pinned host staging, and the top-level call of the
+// recursion driver.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "driver.hpp"
+#include "pluq.h"
+
+using namespace pluq;
+
+namespace {
+
+constexpr uint64_t P_MAX = 1ull << 26;
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+size_t esize(pluq_dtype dt) {
+    switch (dt) {
+    case PLUQ_I64: return 8;
+    case PLUQ_F64: return 8;
+    case PLUQ_I32: return 4;
+    }
+    return 0;
+}
+
+// Largest multiple of 16 such that kchunk * (p/2)^2 + 4p < 2^52.
+int64_t fp64_kchunk(uint64_t p) {
+    const double half = (double)(p / 2);
+    const double lim = 4503599627370496.0 - 4.0 * (double)p;  // 2^52 - 4p
+    double k = half > 0 ? lim / (half * half) : 1e18;
+    if (k > (double)(1 << 30)) k = (double)(1 << 30);
+    int64_t kc = (int64_t)k;
+    kc -= kc % 16;
+    return kc;
+}
+
+struct Pinned {
+    int32_t *idx = nullptr;
+    size_t idx_cap = 0;
+    int32_t *stat = nullptr;
+    int64_t *pq = nullptr;
+    size_t pq_cap = 0;
+};
+
+thread_local Pinned g_pin;
+
+bool ensure_pinned(size_t idx_elems, size_t pq_elems) {
+    if (!g_pin.stat) {
+        if (hipHostMalloc((void **)&g_pin.stat, STAT_WORDS * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+            g_pin.stat = nullptr;
+            return false;
+        }
+    }
+    if (g_pin.idx_cap < idx_elems) {
+        if (g_pin.idx) (void)hipHostFree(g_pin.idx);
+        g_pin.idx = nullptr;
+        g_pin.idx_cap = 0;
+        if (hipHostMalloc((void **)&g_pin.idx, idx_elems * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+            return false;
+        g_pin.idx_cap = idx_elems;
+    }
+    if (g_pin.pq_cap < pq_elems) {
+        if (g_pin.pq) (void)hipHostFree(g_pin.pq);
+        g_pin.pq = nullptr;
+        g_pin.pq_cap = 0;
+        if (hipHostMalloc((void **)&g_pin.pq, pq_elems * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+            return false;
+        g_pin.pq_cap = pq_elems;
+    }
+    return true;
+}
+
+std::once_flag g_bc_once;
+int g_bc_cap = 0;
+
+// Base-case tile capacity: a tile of m*n 32-bit words plus one byte per
+// column must fit the LDS a work-group may use on this device.
+int bc_cap() {
+    std::call_once(g_bc_once, [] {
+        int dev = 0;
+        size_t lds = 65536;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            lds = prop.sharedMemPerBlock;
+        int64_t cap = bc_capacity();
+        if (bc_init() != hipSuccess) lds = std::min<size_t>(lds, 65536);
+        const int64_t fit = (int64_t)(lds > 1024 ? lds - 1024 : 0) / 5;
+        g_bc_cap = (int)std::max<int64_t>(16, std::min(cap, fit));
+    });
+    return g_bc_cap;
+}
+
+struct Layout {
+    size_t stat_off, idx_off, scratch_off, total;
+    size_t idx_elems, scratch_bytes;
+};
+
+Layout layout(int64_t m, int64_t n, size_t esz) {
+    Layout L;
+    L.idx_elems = (size_t)(4 * (m + n) + 65536);
+    const size_t full = (size_t)m * (size_t)n * esz;
+    const size_t strip = (size_t)64 * (size_t)std::max<int64_t>(std::max<int64_t>(m, n), 1) * esz;
+    L.scratch_bytes = std::max(std::min(full, (size_t)256 << 20), std::min(full, strip));
+    if (L.scratch_bytes == 0) L.scratch_bytes = ALIGN;
+    L.stat_off = 0;
+    L.idx_off = align_up(STAT_WORDS * sizeof(int32_t));
+    L.scratch_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
+    L.total = L.scratch_off + align_up(L.scratch_bytes);
+    return L;
+}
+
+pluq_status check_common(int64_t m, int64_t n, int64_t lda, pluq_dtype dt, uint64_t p, const pluq_opts *o) {
+    if (m < 0 || n < 0 || m > (1ll << 31) - 2 || n > (1ll << 31) - 2) return PLUQ_ERR_ARG;
+    if (esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (lda < std::max<int64_t>(1, n)) return PLUQ_ERR_ARG;
+    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
+    if (o) {
+        if (o->form != PLUQ_FORM_FP64 && o->form != PLUQ_FORM_INT8 && o->form != PLUQ_FORM_FP32) return PLUQ_ERR_ARG;
+        if (o->trsm_leaf_override < 0 || o->trsm_leaf_override > 64 || o->cutoff_override < 0) return PLUQ_ERR_ARG;
+    }
+    return PLUQ_OK;
+}
+
+pluq_status form_check(int form, uint64_t p) {
+    if (form == PLUQ_FORM_FP64) return fp64_kchunk(p) >= 16 ? PLUQ_OK : PLUQ_ERR_UNSUPPORTED;
+    return PLUQ_ERR_UNSUPPORTED;  // other forms: not available in this build
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pluq_status_string(pluq_status s) {
+    switch (s) {
+    case PLUQ_OK: return "ok";
+    case PLUQ_ERR_ARG: return "invalid argument";
+    case PLUQ_ERR_MODULUS: return "modulus outside [2, 2^26)";
+    case PLUQ_ERR_RANGE: return "entry outside [0, p)";
+    case PLUQ_ERR_UNSUPPORTED: return "form cannot be exact for this modulus";
+    case PLUQ_ERR_NOMEM: return "host allocation failed";
+    case PLUQ_ERR_DEVICE: return "device (HIP) error";
+    case PLUQ_ERR_WORKSPACE: return "workspace too small";
+    }
+    return "unknown status";
+}
+
+const char *pluq_version(void) { return "pluq-mi355x 0.1 (gfx950)"; }
+
+size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
+    if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
+    return layout(m, n, esize(dt)).total;
+}
+
+pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
+                      int64_t *dQ, int64_t *r_out, const pluq_opts *opts, void *dWork, size_t work_bytes,
+                      void *stream) {
+    pluq_status s = check_common(m, n, lda, dt, p, opts);
+    if (s != PLUQ_OK) return s;
+    if (!r_out) return PLUQ_ERR_ARG;
+    if (m > 0 && n > 0 && !dA) return PLUQ_ERR_ARG;
+    if ((m > 0 && !dP) || (n > 0 && !dQ)) return PLUQ_ERR_ARG;
+    const int form = opts ? opts->form : PLUQ_FORM_FP64;
+    if ((s = form_check(form, p)) != PLUQ_OK) return s;
+    const size_t esz = esize(dt);
+    const Layout L = layout(m, n, esz);
+    if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
+    if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
+
+    Stats stats;
+    try {
+        if (!ensure_pinned(L.idx_elems, (size_t)std::max<int64_t>(m, n))) return PLUQ_ERR_NOMEM;
+        Ctx c;
+        c.dt = (int)dt;
+        c.esz = esz;
+        c.p = p;
+        c.form = form;
+        c.kchunk = (int)std::min<int64_t>(fp64_kchunk(p), 1 << 30);
+        c.leaf_nb = (opts && opts->trsm_leaf_override > 0) ? opts->trsm_leaf_override : 64;
+        c.cap = bc_cap();
+        if (opts && opts->cutoff_override > 0) c.cap = std::min<int64_t>(c.cap, opts->cutoff_override);
+        c.A = (char *)dA;
+        c.lda = lda;
+        c.st = (hipStream_t)stream;
+        char *w = (char *)dWork;
+        c.d_stat = (int32_t *)(w + L.stat_off);
+        c.d_idx = (int32_t *)(w + L.idx_off);
+        c.idx_cap = L.idx_elems;
+        c.scratch = w + L.scratch_off;
+        c.scratch_bytes = L.scratch_bytes;
+        c.h_idx = g_pin.idx;
+        c.h_stat = g_pin.stat;
+
+        std::vector<int32_t> prow, pcol;
+        int64_t r = 0;
+        if (m > 0 && n > 0) {
+            if (opts && opts->validate_entries) {
+                const int32_t g = c.next_gen();
+                c.check(launch_rangescan(c.dt, dA, lda, m, n, (double)p, c.d_stat + STAT_FLAG, g, c.st));
+                c.read_status(STAT_FLAG, 1);
+                if (c.h_stat[STAT_FLAG] == g) {
+                    g_last_stats = c.stats;
+                    return PLUQ_ERR_RANGE;
+                }
+            }
+            r = c.node(0, 0, m, n, Z_UNKNOWN, prow, pcol);
+        } else {
+            prow.resize((size_t)m);
+            pcol.resize((size_t)n);
+            for (int64_t i = 0; i < m; ++i) prow[(size_t)i] = (int32_t)i;
+            for (int64_t j = 0; j < n; ++j) pcol[(size_t)j] = (int32_t)j;
+        }
+        // P and Q to the device (int64)
+        if (m > 0) {
+            for (int64_t i = 0; i < m; ++i) g_pin.pq[i] = prow[(size_t)i];
+            c.check(hipMemcpyAsync(dP, g_pin.pq, (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
+            c.sync();
+        }
+        if (n > 0) {
+            for (int64_t j = 0; j < n; ++j) g_pin.pq[j] = pcol[(size_t)j];
+            c.check(hipMemcpyAsync(dQ, g_pin.pq, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
+            c.sync();
+        }
+        *r_out = r;
+        stats = c.stats;
+        g_prof.resolve();
+    } catch (const DeviceError &) {
+        g_prof.discard();
+        return PLUQ_ERR_DEVICE;
+    } catch (const std::bad_alloc &) {
+        g_prof.discard();
+        return PLUQ_ERR_NOMEM;
+    }
+    g_last_stats = stats;
+    return PLUQ_OK;
+}
+
+pluq_status pluq_rank_profiles(int64_t m, int64_t n, int64_t r, const int64_t *P, const int64_t *Q,
+                               int64_t *row_rp, int64_t *col_rp) {
+    if (m < 0 || n < 0 || r < 0 || r > std::min(m, n)) return PLUQ_ERR_ARG;
+    if (r > 0 && (!P || !Q || !row_rp || !col_rp)) return PLUQ_ERR_ARG;
+    std::copy(P, P + r, row_rp);
+    std::copy(Q, Q + r, col_rp);
+    std::sort(row_rp, row_rp + r);
+    std::sort(col_rp, col_rp + r);
+    return PLUQ_OK;
+}
+
+pluq_status pluq_leading_rank_profiles(int64_t m, int64_t n, int64_t r, const int64_t *P, const int64_t *Q,
+                                       int64_t k, int64_t t, int64_t *rows, int64_t *cols, int64_t *count) {
+    if (m < 0 || n < 0 || r < 0 || r > std::min(m, n) || k < 0 || t < 0 || k > m || t > n || !count)
+        return PLUQ_ERR_ARG;
+    if (r > 0 && (!P || !Q || !rows || !cols)) return PLUQ_ERR_ARG;
+    int64_t c = 0;
+    for (int64_t s = 0; s < r; ++s)
+        if (P[s] < k && Q[s] < t) {
+            rows[c] = P[s];
+            cols[c] = Q[s];
+            ++c;
+        }
+    std::sort(rows, rows + c);
+    std::sort(cols, cols + c);
+    *count = c;
+    return PLUQ_OK;
+}
+
+size_t pluq_batched_workspace_size(int64_t batch, const int64_t *m, const int64_t *n, pluq_dtype dt, uint64_t p,
+                                   const pluq_opts *opts) {
+    (void)batch; (void)m; (void)n; (void)dt; (void)p; (void)opts;
+    return 0;
+}
+
+pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n, void *const *dA,
+                              const int64_t *lda, pluq_dtype dt, uint64_t p, int64_t *const *dP,
+                              int64_t *const *dQ, int64_t *d_r, const pluq_opts *opts, void *dWork,
+                              size_t work_bytes, void *stream) {
+    (void)batch; (void)m; (void)n; (void)dA; (void)lda; (void)dt; (void)p; (void)dP; (void)dQ; (void)d_r;
+    (void)opts; (void)dWork; (void)work_bytes; (void)stream;
+    return PLUQ_ERR_UNSUPPORTED;
+}
+
+size_t pluq_modmm_workspace_size(int64_t m, int64_t n, int64_t k, int32_t form) {
+    (void)m; (void)n; (void)k; (void)form;
+    return 0;
+}
+
+pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
+                       const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form, void *dWork,
+                       size_t work_bytes, void *stream) {
+    (void)dWork; (void)work_bytes;
+    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return PLUQ_ERR_ARG;
+    if (esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
+    pluq_status s = form_check(form, p);
+    if (s != PLUQ_OK) return s;
+    if (m == 0 || n == 0) return PLUQ_OK;
+    if (!dC || (k > 0 && (!dA || !dB))) return PLUQ_ERR_ARG;
+    if (ldc < n || (k > 0 && (lda < k || ldb < n))) return PLUQ_ERR_ARG;
+    if (k == 0) return PLUQ_OK;
+    MMProblem pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.C = dC;
+    pb.ldc = ldc;
+    pb.M = (int32_t)m;
+    pb.N = (int32_t)n;
+    pb.A[0] = dA;
+    pb.lda[0] = lda;
+    pb.B[0] = dB;
+    pb.ldb[0] = ldb;
+    pb.K[0] = (int32_t)k;
+    hipError_t e = launch_modmm_f64((int)dt, &pb, 1, (double)p, (int)fp64_kchunk(p), (hipStream_t)stream);
+    return e == hipSuccess ? PLUQ_OK : PLUQ_ERR_DEVICE;
+}
+
+pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT, int64_t ldt, void *dB, int64_t ldb,
+                      pluq_dtype dt, uint64_t p, int32_t form, void *dWork, size_t work_bytes, void *stream) {
+    (void)dWork; (void)work_bytes;
+    if ((side != 0 && side != 1) || r < 0 || other < 0 || r > INT32_MAX || other > INT32_MAX) return PLUQ_ERR_ARG;
+    if (esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
+    pluq_status s = form_check(form, p);
+    if (s != PLUQ_OK) return s;
+    if (r == 0 || other == 0) return PLUQ_OK;
+    if (!dT || !dB || ldt < r) return PLUQ_ERR_ARG;
+    if (side == 0 && ldb < other) return PLUQ_ERR_ARG;
+    if (side == 1 && ldb < r) return PLUQ_ERR_ARG;
+    // The triangle and B are separate buffers here; run the recursive
+    // solve of the driver with a context whose "matrix" is addressed by
+    // absolute pointers: use two contexts' worth of arithmetic on offsets.
+    try {
+        Ctx c;
+        c.dt = (int)dt;
+        c.esz = esize(dt);
+        c.p = p;
+        c.form = form;
+        c.kchunk = (int)fp64_kchunk(p);
+        c.leaf_nb = 64;
+        c.st = (hipStream_t)stream;
+        // Address both operands relative to the lower of the two pointers
+        // with a common leading dimension is not possible in general, so
+        // solve blockwise here with explicit pointers.
+        const char *T = (const char *)dT;
+        char *B = (char *)dB;
+        const size_t esz = c.esz;
+        auto Tp = [&](int64_t i, int64_t j) { return (const void *)(T + ((size_t)i * ldt + j) * esz); };
+        auto Bp = [&](int64_t i, int64_t j) { return (void *)(B + ((size_t)i * ldb + j) * esz); };
+        const int64_t nb = 64;
+        if (side == 0) {
+            // blocked forward substitution: B_i <- L_ii^{-1} (B_i - sum_{j<i} L_ij B_j)
+            for (int64_t i0 = 0; i0 < r; i0 += nb) {
+                const int64_t bi = std::min(nb, r - i0);
+                if (i0 > 0) {
+                    MMProblem pb;
+                    std::memset(&pb, 0, sizeof(pb));
+                    pb.C = Bp(i0, 0); pb.ldc = ldb; pb.M = (int32_t)bi; pb.N = (int32_t)other;
+                    pb.A[0] = Tp(i0, 0); pb.lda[0] = ldt; pb.B[0] = Bp(0, 0); pb.ldb[0] = ldb; pb.K[0] = (int32_t)i0;
+                    c.check(launch_modmm_f64(c.dt, &pb, 1, (double)p, c.kchunk, c.st));
+                }
+                c.check(launch_trsm_llu_leaf(c.dt, Tp(i0, i0), ldt, (int)bi, Bp(i0, 0), ldb, other, (double)p, c.kchunk, c.st));
+            }
+        } else {
+            // blocked: B_:j <- (B_:j - sum_{i<j} B_:i U_ij) U_jj^{-1}
+            for (int64_t j0 = 0; j0 < r; j0 += nb) {
+                const int64_t bj = std::min(nb, r - j0);
+                if (j0 > 0) {
+                    MMProblem pb;
+                    std::memset(&pb, 0, sizeof(pb));
+                    pb.C = Bp(0, j0); pb.ldc = ldb; pb.M = (int32_t)other; pb.N = (int32_t)bj;
+                    pb.A[0] = Bp(0, 0); pb.lda[0] = ldb; pb.B[0] = Tp(0, j0); pb.ldb[0] = ldt; pb.K[0] = (int32_t)j0;
+                    c.check(launch_modmm_f64(c.dt, &pb, 1, (double)p, c.kchunk, c.st));
+                }
+                c.check(launch_trsm_run_leaf(c.dt, Bp(0, j0), ldb, other, Tp(j0, j0), ldt, (int)bj, (double)p, c.kchunk, c.st));
+            }
+        }
+    } catch (const DeviceError &) {
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
+}
+
+void pluq_profile_enable(int32_t mask) {
+    for (int c = 0; c < KCLASSES; ++c) g_prof.k[c] = KStat();
+    g_prof.discard();
+    g_prof.mask = mask;
+}
+
+void pluq_profile_read(pluq_kernel_stat *out) {
+    if (!out) return;
+    for (int c = 0; c < KCLASSES; ++c) {
+        out[c].launches = g_prof.k[c].launches;
+        out[c].ms = g_prof.k[c].ms;
+        out[c].flops = g_prof.k[c].flops;
+        out[c].bytes = g_prof.k[c].bytes;
+    }
+}
+
+void pluq_last_stats(int64_t *nodes, int64_t *basecases, int64_t *launches, int64_t *syncs) {
+    if (nodes) *nodes = g_last_stats.nodes;
+    if (basecases) *basecases = g_last_stats.basecases;
+    if (launches) *launches = g_last_stats.launches;
+    if (syncs) *syncs = g_last_stats.syncs;
+}
+
+}  // extern "C"

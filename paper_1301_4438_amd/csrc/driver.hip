@@ -1,0 +1,510 @@
+// Host driver of the quad recursion (Algorithm 1, Section 2).
+//
+// node() follows the algorithm's block steps on the device-resident matrix:
+//   PLUQ(A1); PermR(A2, P1^T); PermC(A3, Q1^T);
+//   D <- L1^{-1} B1; E <- C1 U1^{-1};
+//   F <- B2 - M1 D; G <- C2 - E V1; H <- A4 - E D        (one grouped MM launch)
+//   PLUQ(F); PLUQ(G);
+//   H <- P3^T H Q2^T; E <- P3^T E; M1 <- P2^T M1; D <- D Q2^T; V1 <- V1 Q3^T;
+//   [I; K] <- [H1; H3] U2^{-1};
+//   O <- L3^{-1} (H2 - I V2)   (= N - J V2 with J = L3^{-1} I, N = L3^{-1} H2,
+//                               exact over the field, so no copy of I needed);
+//   R <- H4 - K V2 - M3 O                                (one MM launch, 2 pairs)
+//   PLUQ(R); P4^T [E2 M3 0 K]; [D2; V2; 0; O] Q4^T;
+//   A <- S^T A T^T (block rotations of rows and columns).
+// A block known to be zero (from the zero flags the MM epilogues raise, or a
+// scan) returns rank 0 with identity permutations.  Tiles small enough for
+// the LDS go to the base case.  The driver needs the ranks r_i, so it reads
+// them back after each base case; permutation vectors are composed on the
+// host (they are index bookkeeping) and uploaded only when a permutation is
+// not the identity.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "driver.hpp"
+
+namespace pluq {
+
+thread_local Stats g_last_stats;
+thread_local Profiler g_prof;
+
+hipError_t Profiler::begin(hipStream_t st, size_t *idx) {
+    while (pool.size() < used + 2) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        pool.push_back(e);
+    }
+    *idx = used;
+    used += 2;
+    return hipEventRecord(pool[*idx], st);
+}
+
+hipError_t Profiler::end(hipStream_t st, size_t idx, int cls, double flops, double bytes) {
+    pending.push_back({cls, idx, flops, bytes});
+    return hipEventRecord(pool[idx + 1], st);
+}
+
+void Profiler::resolve() {
+    for (const Pending &q : pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pool[q.e0], pool[q.e0 + 1]) == hipSuccess) {
+            k[q.cls].launches++;
+            k[q.cls].ms += ms;
+            k[q.cls].flops += q.flops;
+            k[q.cls].bytes += q.bytes;
+        }
+    }
+    discard();
+}
+
+void Profiler::discard() {
+    pending.clear();
+    used = 0;
+}
+
+// ---------------------------------------------------------------- helpers --
+
+static bool is_identity(const std::vector<int32_t> &v) {
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i] != (int32_t)i) return false;
+    return true;
+}
+
+// A gather map must be a permutation of [0, n): checked before any upload
+// so that no kernel can index outside its block.
+static void require_permutation(const std::vector<int32_t> &v) {
+    std::vector<char> seen(v.size(), 0);
+    for (int32_t x : v) {
+        if (x < 0 || (size_t)x >= v.size() || seen[(size_t)x]) throw DeviceError{hipErrorInvalidValue};
+        seen[(size_t)x] = 1;
+    }
+}
+
+static void iota(std::vector<int32_t> &v, int64_t n) {
+    v.resize((size_t)n);
+    std::iota(v.begin(), v.end(), 0);
+}
+
+void Ctx::check(hipError_t e) {
+    if (e != hipSuccess) throw DeviceError{e};
+}
+
+char *Ctx::at(int64_t i, int64_t j) const { return A + ((size_t)i * (size_t)lda + (size_t)j) * esz; }
+
+void Ctx::sync() {
+    check(hipStreamSynchronize(st));
+    idx_used = 0;
+    stats.syncs++;
+}
+
+const int32_t *Ctx::upload(const int32_t *v, int64_t n) {
+    const size_t need = ((size_t)n + 63) & ~(size_t)63;
+    if (idx_used + need > idx_cap) sync();
+    if (need > idx_cap) throw DeviceError{hipErrorOutOfMemory};
+    std::memcpy(h_idx + idx_used, v, (size_t)n * sizeof(int32_t));
+    check(hipMemcpyAsync(d_idx + idx_used, h_idx + idx_used, (size_t)n * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st));
+    const int32_t *d = d_idx + idx_used;
+    idx_used += need;
+    return d;
+}
+
+int32_t Ctx::next_gen() {
+    gen = (gen % 2000000000) + 1;
+    return gen;
+}
+
+// Read `count` int32 status words back (synchronising).
+void Ctx::read_status(int64_t offset, int64_t count) {
+    check(hipMemcpyAsync(h_stat + offset, d_stat + offset, (size_t)count * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, st));
+    sync();
+}
+
+// ------------------------------------------------------------ permutations --
+
+// Rows of the nr x nc block at (gi, gj): new row t = old row map[t].
+void Ctx::perm_rows(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map) {
+    if (nr <= 1 || nc <= 0 || is_identity(map)) return;
+    if ((int64_t)map.size() != nr) throw DeviceError{hipErrorInvalidValue};
+    require_permutation(map);
+    const int32_t *dmap = upload(map.data(), nr);
+    const int64_t w = std::max<int64_t>(1, std::min<int64_t>(nc, (int64_t)(scratch_bytes / esz) / nr));
+    for (int64_t c0 = 0; c0 < nc; c0 += w) {
+        const int64_t cw = std::min(w, nc - c0);
+        const double bytes = 2.0 * (double)nr * (double)cw * (double)esz;
+        launch(K_PERM, 0, bytes, [&] { return launch_gather2d(dt, at(gi, gj + c0), lda, scratch, cw, nr, cw, dmap, nullptr, st); });
+        launch(K_PERM, 0, bytes, [&] { return launch_gather2d(dt, scratch, cw, at(gi, gj + c0), lda, nr, cw, nullptr, nullptr, st); });
+    }
+}
+
+// Columns of the nr x nc block at (gi, gj): new column t = old column map[t].
+void Ctx::perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map) {
+    if (nc <= 1 || nr <= 0 || is_identity(map)) return;
+    if ((int64_t)map.size() != nc) throw DeviceError{hipErrorInvalidValue};
+    require_permutation(map);
+    const int32_t *dmap = upload(map.data(), nc);
+    const int64_t h = std::max<int64_t>(1, std::min<int64_t>(nr, (int64_t)(scratch_bytes / esz) / nc));
+    for (int64_t r0 = 0; r0 < nr; r0 += h) {
+        const int64_t rh = std::min(h, nr - r0);
+        const double bytes = 2.0 * (double)rh * (double)nc * (double)esz;
+        launch(K_PERM, 0, bytes, [&] { return launch_gather2d(dt, at(gi + r0, gj), lda, scratch, nc, rh, nc, nullptr, dmap, st); });
+        launch(K_PERM, 0, bytes, [&] { return launch_gather2d(dt, scratch, nc, at(gi + r0, gj), lda, rh, nc, nullptr, nullptr, st); });
+    }
+}
+
+// -------------------------------------------------------------------- MM --
+
+void Ctx::mm(MMProblem *probs, int n) {
+    int live = 0;
+    for (int q = 0; q < n; ++q)
+        if (probs[q].M > 0 && probs[q].N > 0 && (probs[q].K[0] > 0 || probs[q].K[1] > 0)) probs[live++] = probs[q];
+    if (!live) return;
+    double flops = 0, bytes = 0;
+    for (int q = 0; q < live; ++q) {
+        const double M = probs[q].M, N = probs[q].N;
+        bytes += 2.0 * M * N;
+        for (int s = 0; s < 2; ++s) {
+            const double K = probs[q].K[s] > 0 ? probs[q].K[s] : 0;
+            flops += 2.0 * M * N * K;
+            bytes += M * K + K * N;
+        }
+    }
+    launch(K_MODMM, flops, bytes * (double)esz, [&] { return launch_modmm_f64(dt, probs, live, (double)p, kchunk, st); });
+}
+
+static MMProblem mmprob(void *C, int64_t ldc, int64_t M, int64_t N) {
+    MMProblem pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.C = C;
+    pb.ldc = ldc;
+    pb.M = (int32_t)M;
+    pb.N = (int32_t)N;
+    return pb;
+}
+
+static void mmpair(MMProblem &pb, int s, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t K) {
+    pb.A[s] = A;
+    pb.lda[s] = lda;
+    pb.B[s] = B;
+    pb.ldb[s] = ldb;
+    pb.K[s] = (int32_t)K;
+}
+
+// ------------------------------------------------------------------ TRSM --
+
+static int64_t trsm_split(int64_t r) {
+    int64_t h = r / 2;
+    if (h >= 64) h -= h % 64;
+    return h;
+}
+
+// B (r x ncols at (bi, bj)) <- L^{-1} B, L unit lower r x r at (li, lj).
+void Ctx::trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols) {
+    if (r <= 0 || ncols <= 0) return;
+    if (r <= leaf_nb) {
+        launch(K_TRSM, 0, (2.0 * r * ncols + r * r) * esz,
+               [&] { return launch_trsm_llu_leaf(dt, at(li, lj), lda, (int)r, at(bi, bj), lda, ncols, (double)p, kchunk, st); });
+        return;
+    }
+    const int64_t r1 = trsm_split(r);
+    trsm_llu(li, lj, r1, bi, bj, ncols);
+    MMProblem pb = mmprob(at(bi + r1, bj), lda, r - r1, ncols);
+    mmpair(pb, 0, at(li + r1, lj), lda, at(bi, bj), lda, r1);
+    mm(&pb, 1);
+    trsm_llu(li + r1, lj + r1, r - r1, bi + r1, bj, ncols);
+}
+
+// B (nrows x r at (bi, bj)) <- B U^{-1}, U upper r x r at (ui, uj).
+void Ctx::trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r) {
+    if (r <= 0 || nrows <= 0) return;
+    if (r <= leaf_nb) {
+        launch(K_TRSM, 0, (2.0 * r * nrows + r * r) * esz,
+               [&] { return launch_trsm_run_leaf(dt, at(bi, bj), lda, nrows, at(ui, uj), lda, (int)r, (double)p, kchunk, st); });
+        return;
+    }
+    const int64_t r1 = trsm_split(r);
+    trsm_run(bi, bj, nrows, ui, uj, r1);
+    MMProblem pb = mmprob(at(bi, bj + r1), lda, nrows, r - r1);
+    mmpair(pb, 0, at(bi, bj), lda, at(ui, uj + r1), lda, r1);
+    mm(&pb, 1);
+    trsm_run(bi, bj + r1, nrows, ui + r1, uj + r1, r - r1);
+}
+
+// ------------------------------------------------------------- base case --
+
+// Pivot order of Algorithm 1 for the RPM given by rpm_col (row -> column or
+// -1): the recursion visits A1, F, G, R on floor(|rows|/2) x floor(|cols|/2)
+// splits of the remaining index sets; a single row or column holds at most
+// one pivot.  Appends pivots to (pr, pc).
+static void zorder_rec(const std::vector<int32_t> &rows, const std::vector<int32_t> &cols,
+                       const std::vector<int32_t> &rpm_col, const std::vector<int32_t> &colpos,
+                       std::vector<int32_t> &pr, std::vector<int32_t> &pc, std::vector<int32_t> &mark,
+                       int32_t &stamp) {
+    if (rows.empty() || cols.empty()) return;
+    // mark the columns of this call
+    const int32_t my = ++stamp;
+    for (int32_t c : cols) mark[c] = my;
+    int npiv = 0, last = -1;
+    for (int32_t i : rows) {
+        const int32_t c = rpm_col[i];
+        if (c >= 0 && mark[c] == my) { ++npiv; last = i; }
+    }
+    if (npiv == 0) return;
+    if (rows.size() == 1 || cols.size() == 1) {
+        pr.push_back(last);
+        pc.push_back(rpm_col[last]);
+        return;
+    }
+    const size_t k = rows.size() / 2, h = cols.size() / 2;
+    std::vector<int32_t> r_top(rows.begin(), rows.begin() + k), r_bot(rows.begin() + k, rows.end());
+    std::vector<int32_t> c_left(cols.begin(), cols.begin() + h), c_right(cols.begin() + h, cols.end());
+    auto minus = [&](const std::vector<int32_t> &src, const std::vector<int32_t> &rem) {
+        const int32_t s2 = ++stamp;
+        for (int32_t x : rem) mark[x] = s2;
+        std::vector<int32_t> out;
+        out.reserve(src.size());
+        for (int32_t x : src)
+            if (mark[x] != s2) out.push_back(x);
+        return out;
+    };
+    (void)colpos;
+    const size_t s1 = pr.size();
+    zorder_rec(r_top, c_left, rpm_col, colpos, pr, pc, mark, stamp);                 // A1
+    const size_t e1 = pr.size();
+    std::vector<int32_t> rows1(pr.begin() + s1, pr.begin() + e1), cols1(pc.begin() + s1, pc.begin() + e1);
+    zorder_rec(minus(r_top, rows1), c_right, rpm_col, colpos, pr, pc, mark, stamp);  // F
+    const size_t e2 = pr.size();
+    std::vector<int32_t> cols2(pc.begin() + e1, pc.begin() + e2);
+    zorder_rec(r_bot, minus(c_left, cols1), rpm_col, colpos, pr, pc, mark, stamp);   // G
+    const size_t e3 = pr.size();
+    std::vector<int32_t> rows3(pr.begin() + e2, pr.begin() + e3);
+    zorder_rec(minus(r_bot, rows3), minus(c_right, cols2), rpm_col, colpos, pr, pc, mark, stamp);  // R
+}
+
+void zorder_from_rpm(int64_t m, int64_t n, const int32_t *rpm_col_in, std::vector<int32_t> &prow,
+                     std::vector<int32_t> &pcol) {
+    std::vector<int32_t> rows((size_t)m), cols((size_t)n), rpm(rpm_col_in, rpm_col_in + m), colpos;
+    std::iota(rows.begin(), rows.end(), 0);
+    std::iota(cols.begin(), cols.end(), 0);
+    std::vector<int32_t> pr, pc, mark((size_t)std::max(m, n), 0);
+    int32_t stamp = 0;
+    // the marks are shared by rows and columns; use separate stamps via one array
+    // sized max(m, n): rows and columns are never marked in the same pass.
+    zorder_rec(rows, cols, rpm, colpos, pr, pc, mark, stamp);
+    std::vector<char> rowp((size_t)m, 0), colp((size_t)n, 0);
+    prow = pr;
+    pcol = pc;
+    for (int32_t x : pr) rowp[x] = 1;
+    for (int32_t x : pc) colp[x] = 1;
+    for (int64_t i = 0; i < m; ++i)
+        if (!rowp[i]) prow.push_back((int32_t)i);
+    for (int64_t j = 0; j < n; ++j)
+        if (!colp[j]) pcol.push_back((int32_t)j);
+}
+
+int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<int32_t> &prow,
+                      std::vector<int32_t> &pcol) {
+    stats.basecases++;
+    // optimistic: the identity order (generic rank profile)
+    const double tbytes = 2.0 * m * n * esz;
+    launch(K_BASE, 0, tbytes, [&] {
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, d_stat + STAT_BC, st);
+    });
+    read_status(STAT_BC, 2);
+    if (h_stat[STAT_BC + 1] == 1) {
+        iota(prow, m);
+        iota(pcol, n);
+        return h_stat[STAT_BC];
+    }
+    // general: rank profile matrix, then the pivot order, then the ordered LU
+    launch(K_BASE, 0, 1.0 * m * n * esz,
+           [&] { return launch_bc_rpm(dt, at(gi, gj), lda, (int)m, (int)n, (double)p, d_stat + STAT_BC, st); });
+    read_status(STAT_BC, 1 + m);
+    const int64_t r = h_stat[STAT_BC];
+    for (int64_t i = 0; i < m; ++i)
+        if (h_stat[STAT_BC + 1 + i] < -1 || h_stat[STAT_BC + 1 + i] >= n) throw DeviceError{hipErrorInvalidValue};
+    zorder_from_rpm(m, n, h_stat + STAT_BC + 1, prow, pcol);
+    if ((int64_t)prow.size() != m || (int64_t)pcol.size() != n) throw DeviceError{hipErrorInvalidValue};
+    require_permutation(prow);
+    require_permutation(pcol);
+    const int32_t *drow = upload(prow.data(), m);
+    const int32_t *dcol = upload(pcol.data(), n);
+    launch(K_BASE, 0, tbytes, [&] {
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, d_stat + STAT_BC, st);
+    });
+    return r;
+}
+
+// ------------------------------------------------------------ zero flags --
+
+// Resolve the zero status of up to 4 blocks with one synchronisation.
+void Ctx::resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens) {
+    bool need = false;
+    int32_t g[8];
+    for (int b = 0; b < nb; ++b) {
+        g[b] = gens ? gens[b] : 0;
+        if (z[b] != Z_UNKNOWN) continue;
+        if (blk[b].m <= 0 || blk[b].n <= 0) { z[b] = Z_ZERO; continue; }
+        if (!g[b]) {
+            g[b] = next_gen();
+            launch(K_SCAN, 0, (double)blk[b].m * blk[b].n * esz, [&] {
+                return launch_zscan(dt, at(blk[b].i, blk[b].j), lda, blk[b].m, blk[b].n, d_stat + STAT_FLAG + b, g[b], st);
+            });
+        }
+        need = true;
+    }
+    if (!need) return;
+    read_status(STAT_FLAG, nb);
+    for (int b = 0; b < nb; ++b)
+        if (z[b] == Z_UNKNOWN) z[b] = (h_stat[STAT_FLAG + b] == g[b]) ? Z_NONZERO : Z_ZERO;
+}
+
+// ------------------------------------------------------------------ node --
+
+int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vector<int32_t> &prow,
+                  std::vector<int32_t> &pcol) {
+    stats.nodes++;
+    if (m <= 0 || n <= 0 || z == Z_ZERO) {
+        iota(prow, m);
+        iota(pcol, n);
+        return 0;
+    }
+    if (m * n <= cap) return basecase(gi, gj, m, n, prow, pcol);
+    if (z == Z_UNKNOWN) {
+        Blk b{gi, gj, m, n};
+        resolve_zero(1, &b, &z, nullptr);
+        if (z == Z_ZERO) {
+            iota(prow, m);
+            iota(pcol, n);
+            return 0;
+        }
+    }
+    const int64_t k = m / 2, h = n / 2;
+
+    // PLUQ(A1)
+    std::vector<int32_t> P1, Q1;
+    const int64_t r1 = node(gi, gj, k, h, Z_UNKNOWN, P1, Q1);
+    perm_rows(gi, gj + h, k, n - h, P1);   // [B1; B2] <- P1^T A2
+    perm_cols(gi + k, gj, m - k, h, Q1);   // [C1 C2] <- A3 Q1^T
+
+    // F = B2 - M1 D, G = C2 - E V1, H = A4 - E D
+    Blk bF{gi + r1, gj + h, k - r1, n - h}, bG{gi + k, gj + r1, m - k, h - r1}, bH{gi + k, gj + h, m - k, n - h};
+    Zero zFGH[3] = {Z_UNKNOWN, Z_UNKNOWN, Z_UNKNOWN};
+    int32_t gFGH[3] = {0, 0, 0};
+    if (r1 > 0) {
+        trsm_llu(gi, gj, r1, gi, gj + h, n - h);       // D <- L1^{-1} B1
+        trsm_run(gi + k, gj, m - k, gi, gj, r1);       // E <- C1 U1^{-1}
+        MMProblem pb[3];
+        pb[0] = mmprob(at(bF.i, bF.j), lda, bF.m, bF.n);
+        mmpair(pb[0], 0, at(gi + r1, gj), lda, at(gi, gj + h), lda, r1);
+        pb[1] = mmprob(at(bG.i, bG.j), lda, bG.m, bG.n);
+        mmpair(pb[1], 0, at(gi + k, gj), lda, at(gi, gj + r1), lda, r1);
+        pb[2] = mmprob(at(bH.i, bH.j), lda, bH.m, bH.n);
+        mmpair(pb[2], 0, at(gi + k, gj), lda, at(gi, gj + h), lda, r1);
+        for (int q = 0; q < 3; ++q) {
+            gFGH[q] = next_gen();
+            pb[q].nzflag = d_stat + STAT_FLAG + q;
+            pb[q].nzgen = gFGH[q];
+        }
+        mm(pb, 3);
+    }
+    {
+        Blk bl[3] = {bF, bG, bH};
+        resolve_zero(3, bl, zFGH, r1 > 0 ? gFGH : nullptr);
+    }
+
+    std::vector<int32_t> P2, Q2, P3, Q3;
+    const int64_t r2 = node(bF.i, bF.j, bF.m, bF.n, zFGH[0], P2, Q2);   // PLUQ(F)
+    const int64_t r3 = node(bG.i, bG.j, bG.m, bG.n, zFGH[1], P3, Q3);   // PLUQ(G)
+
+    perm_rows(gi + r1, gj, k - r1, r1, P2);                    // M1 <- P2^T M1
+    perm_rows(gi + k, gj, m - k, r1, P3);                      // E  <- P3^T E
+    perm_cols(gi, gj + h, r1, n - h, Q2);                      // D  <- D Q2^T
+    perm_cols(gi, gj + r1, r1, h - r1, Q3);                    // V1 <- V1 Q3^T
+    if (zFGH[2] != Z_ZERO) {
+        perm_rows(gi + k, gj + h, m - k, n - h, P3);           // H <- P3^T H Q2^T
+        perm_cols(gi + k, gj + h, m - k, n - h, Q2);
+    }
+
+    // R = H4 - K V2 - M3 O after the solves
+    Blk bR{gi + k + r3, gj + h + r2, m - k - r3, n - h - r2};
+    Zero zR = (zFGH[2] == Z_ZERO) ? Z_ZERO : Z_UNKNOWN;
+    if (zFGH[2] != Z_ZERO) {
+        if (r2 > 0) trsm_run(gi + k, gj + h, m - k, gi + r1, gj + h, r2);   // [I; K] <- [H1; H3] U2^{-1}
+        if (r3 > 0) {
+            if (r2 > 0) {                                                   // H2 <- H2 - I V2
+                MMProblem pb = mmprob(at(gi + k, gj + h + r2), lda, r3, n - h - r2);
+                mmpair(pb, 0, at(gi + k, gj + h), lda, at(gi + r1, gj + h + r2), lda, r2);
+                mm(&pb, 1);
+            }
+            trsm_llu(gi + k, gj + r1, r3, gi + k, gj + h + r2, n - h - r2);  // O <- L3^{-1} H2
+        }
+        if (r2 > 0 || r3 > 0) {
+            MMProblem pb = mmprob(at(bR.i, bR.j), lda, bR.m, bR.n);
+            int s = 0;
+            if (r2 > 0) mmpair(pb, s++, at(gi + k + r3, gj + h), lda, at(gi + r1, gj + h + r2), lda, r2);   // K V2
+            if (r3 > 0) mmpair(pb, s++, at(gi + k + r3, gj + r1), lda, at(gi + k, gj + h + r2), lda, r3);   // M3 O
+            const int32_t gR = next_gen();
+            pb.nzflag = d_stat + STAT_FLAG;
+            pb.nzgen = gR;
+            mm(&pb, 1);
+            resolve_zero(1, &bR, &zR, &gR);
+        } else {
+            zR = zFGH[2];   // R is H itself
+        }
+    }
+
+    std::vector<int32_t> P4, Q4;
+    const int64_t r4 = node(bR.i, bR.j, bR.m, bR.n, zR, P4, Q4);       // PLUQ(R)
+    perm_rows(gi + k + r3, gj, m - k - r3, r1 + r3, P4);               // P4^T [E2 M3]
+    perm_rows(gi + k + r3, gj + h, m - k - r3, r2, P4);                // P4^T K
+    perm_cols(gi, gj + h + r2, r1 + r2, n - h - r2, Q4);               // [D2; V2] Q4^T
+    perm_cols(gi + k, gj + h + r2, r3, n - h - r2, Q4);                // O Q4^T
+
+    // S^T A T^T
+    {
+        const int64_t a = r1 + r2, b = k + r3 + r4;      // row band [a, b)
+        if (k > a && b > k) {
+            std::vector<int32_t> map;
+            map.reserve((size_t)(b - a));
+            for (int64_t t = k; t < b; ++t) map.push_back((int32_t)(t - a));
+            for (int64_t t = a; t < k; ++t) map.push_back((int32_t)(t - a));
+            perm_rows(gi + a, gj, b - a, n, map);
+        }
+        // columns: c0 [0,r1) c1 [r1,r1+r3) c2 [r1+r3,h) c3 [h,h+r2) c4 [h+r2,h+r2+r4) c5 rest
+        // new order c0 c3 c1 c4 c2 c5 over the band [r1, h+r2+r4)
+        const int64_t ca = r1, cb = h + r2 + r4;
+        std::vector<int32_t> map;
+        map.reserve((size_t)(cb - ca));
+        for (int64_t t = h; t < h + r2; ++t) map.push_back((int32_t)(t - ca));
+        for (int64_t t = r1; t < r1 + r3; ++t) map.push_back((int32_t)(t - ca));
+        for (int64_t t = h + r2; t < h + r2 + r4; ++t) map.push_back((int32_t)(t - ca));
+        for (int64_t t = r1 + r3; t < h; ++t) map.push_back((int32_t)(t - ca));
+        perm_cols(gi, gj + ca, m, cb - ca, map);
+    }
+
+    // P = Diag(P1 [I; P2], P3 [I; P4]) S ;  Q = T Diag([I; Q3] Q1, [I; Q4] Q2)
+    prow.clear();
+    prow.reserve((size_t)m);
+    for (int64_t t = 0; t < r1; ++t) prow.push_back(P1[t]);
+    for (int64_t t = 0; t < r2; ++t) prow.push_back(P1[r1 + P2[t]]);
+    for (int64_t t = 0; t < r3; ++t) prow.push_back((int32_t)(k + P3[t]));
+    for (int64_t t = 0; t < r4; ++t) prow.push_back((int32_t)(k + P3[r3 + P4[t]]));
+    for (int64_t t = r2; t < k - r1; ++t) prow.push_back(P1[r1 + P2[t]]);
+    for (int64_t t = r4; t < m - k - r3; ++t) prow.push_back((int32_t)(k + P3[r3 + P4[t]]));
+    pcol.clear();
+    pcol.reserve((size_t)n);
+    for (int64_t t = 0; t < r1; ++t) pcol.push_back(Q1[t]);
+    for (int64_t t = 0; t < r2; ++t) pcol.push_back((int32_t)(h + Q2[t]));
+    for (int64_t t = 0; t < r3; ++t) pcol.push_back(Q1[r1 + Q3[t]]);
+    for (int64_t t = 0; t < r4; ++t) pcol.push_back((int32_t)(h + Q2[r2 + Q4[t]]));
+    for (int64_t t = r3; t < h - r1; ++t) pcol.push_back(Q1[r1 + Q3[t]]);
+    for (int64_t t = r4; t < n - h - r2; ++t) pcol.push_back((int32_t)(h + Q2[r2 + Q4[t]]));
+    return r1 + r2 + r3 + r4;
+}
+
+}  // namespace pluq

@@ -1,0 +1,112 @@
+// Internal state of one decomposition call (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace pluq {
+
+struct DeviceError {
+    hipError_t e;
+};
+
+struct Stats {
+    int64_t nodes = 0, basecases = 0, launches = 0, syncs = 0;
+};
+extern thread_local Stats g_last_stats;
+
+// Per-kernel-class device timing (HIP events), per host thread.
+constexpr int KCLASSES = 5;
+enum KClass { K_MODMM = 0, K_TRSM = 1, K_PERM = 2, K_BASE = 3, K_SCAN = 4 };
+struct KStat {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+};
+struct Profiler {
+    int32_t mask = 0;
+    KStat k[KCLASSES];
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Pending {
+        int cls;
+        size_t e0;
+        double flops, bytes;
+    };
+    std::vector<Pending> pending;
+    hipError_t begin(hipStream_t st, size_t *idx);
+    hipError_t end(hipStream_t st, size_t idx, int cls, double flops, double bytes);
+    void resolve();  // after the stream has been synchronised
+    void discard();
+};
+extern thread_local Profiler g_prof;
+
+enum Zero { Z_UNKNOWN = 0, Z_ZERO = 1, Z_NONZERO = 2 };
+
+struct Blk {
+    int64_t i, j, m, n;
+};
+
+// Layout of the int32 status area in device workspace.
+constexpr int64_t STAT_FLAG = 0;     // 8 zero-flag slots
+constexpr int64_t STAT_BC = 64;      // base-case status: r, ok / rpm columns
+constexpr int64_t STAT_WORDS = 64 + 2 + 16384 + 64;
+
+struct Ctx {
+    // problem
+    int dt = 0;
+    size_t esz = 8;
+    uint64_t p = 0;
+    int form = 0;
+    int kchunk = 16;
+    int leaf_nb = 64;
+    int64_t cap = 16384;
+    char *A = nullptr;
+    int64_t lda = 0;
+    hipStream_t st = nullptr;
+    // device workspace
+    char *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int32_t *d_idx = nullptr;
+    size_t idx_cap = 0, idx_used = 0;
+    int32_t *d_stat = nullptr;
+    // pinned host mirrors
+    int32_t *h_idx = nullptr;
+    int32_t *h_stat = nullptr;
+    int32_t gen = 0;
+    Stats stats;
+
+    void check(hipError_t e);
+    // Issue one kernel launch (f returns its hipError_t), timed when the
+    // profiler is on.
+    template <class F> void launch(int cls, double flops, double bytes, F f) {
+        size_t idx = 0;
+        const bool timed = (g_prof.mask >> cls) & 1;
+        if (timed) check(g_prof.begin(st, &idx));
+        check(f());
+        if (timed) check(g_prof.end(st, idx, cls, flops, bytes));
+        stats.launches++;
+    }
+    char *at(int64_t i, int64_t j) const;
+    void sync();
+    const int32_t *upload(const int32_t *v, int64_t n);
+    int32_t next_gen();
+    void read_status(int64_t offset, int64_t count);
+    void perm_rows(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
+    void perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
+    void mm(MMProblem *probs, int n);
+    void trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols);
+    void trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r);
+    int64_t basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<int32_t> &prow,
+                     std::vector<int32_t> &pcol);
+    void resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens);
+    int64_t node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vector<int32_t> &prow,
+                 std::vector<int32_t> &pcol);
+};
+
+void zorder_from_rpm(int64_t m, int64_t n, const int32_t *rpm_col, std::vector<int32_t> &prow,
+                     std::vector<int32_t> &pcol);
+
+}  // namespace pluq

@@ -1,0 +1,206 @@
+// MM(C, A, B) of Section 2 on the float64 matrix cores of gfx950:
+//     C <- C - sum_s A_s B_s  (mod p)
+// for up to four independent problems per launch (the Schur updates of one
+// recursion level are issued together), each with up to two operand pairs
+// accumulated into the same output (R <- H4 - K V2 - M3 O is one problem).
+//
+// Exactness: operands are mapped to symmetric residues |a| <= p/2, so each
+// product is at most (p/2)^2 and a sum of `kchunk` of them plus a reduced
+// residue stays below 2^52: every partial sum is an exactly representable
+// integer whatever the summation order inside the matrix core.  The
+// accumulator is reduced once per kchunk terms (delayed reduction, Section 6)
+// and once in the epilogue, where C is read, updated and written back.
+//
+// Tiling: 256 threads = 4 waves in a 2 x 2 grid; each wave owns a
+// (BM/2) x (BN/2) sub-tile made of 16 x 16 blocks computed with
+// v_mfma_f64_16x16x4_f64.  A and B panels of depth 16 are staged in LDS with
+// k as the slow index, so the 16 lanes sharing a k read consecutive words.
+// The next panel is fetched into registers while the current one is used.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pluq {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+struct MMArgs {
+    MMProblem prob[MM_MAX_PROBLEMS];
+    int32_t count;
+    int32_t kchunk;
+    ModP mod;
+};
+
+template <typename T, int BM, int BN>
+__global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
+    constexpr int BK = 16;
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 16, FN = WN / 16;
+    constexpr int PAD = 2;
+    constexpr int ELA = BM * BK / 256;   // A elements loaded per thread
+    constexpr int ELB = BN * BK / 256;   // B elements loaded per thread
+    constexpr int TPRA = BK / ELA;       // threads per A row
+    constexpr int TPRB = BN / ELB;       // threads per B row
+    __shared__ double As[BK][BM + PAD];
+    __shared__ double Bs[BK][BN + PAD];
+
+    const int tile = blockIdx.x;
+    int pi = 0;
+#pragma unroll
+    for (int q = 1; q < MM_MAX_PROBLEMS; ++q)
+        if (q < args.count && tile >= args.prob[q].tileStart) pi = q;
+    const MMProblem &P = args.prob[pi];
+    const ModP mod = args.mod;
+    const int t = tile - P.tileStart;
+    const int row0 = (t / P.tilesN) * BM;
+    const int col0 = (t % P.tilesN) * BN;
+    const int M = P.M, N = P.N;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm0 = (wave >> 1) * WM;
+    const int wn0 = (wave & 1) * WN;
+
+    const int ar = tid / TPRA, ak = (tid % TPRA) * ELA;
+    const int bk = tid / TPRB, bc = (tid % TPRB) * ELB;
+
+    const int K0 = P.K[0], K1 = P.K[1];
+    const int steps0 = (K0 + BK - 1) / BK;
+    const int steps = steps0 + (K1 + BK - 1) / BK;
+
+    v4d acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+    double ra[ELA], rb[ELB];
+    auto load_step = [&](int s) {
+        const int pair = (s < steps0) ? 0 : 1;
+        const int k0 = (pair == 0 ? s : s - steps0) * BK;
+        const int K = pair == 0 ? K0 : K1;
+        const T *A = (const T *)P.A[pair];
+        const T *B = (const T *)P.B[pair];
+        const int64_t lda = P.lda[pair], ldb = P.ldb[pair];
+        const int grow = row0 + ar;
+#pragma unroll
+        for (int e = 0; e < ELA; ++e) {
+            const int kk = k0 + ak + e;
+            double v = 0.0;
+            if (grow < M && kk < K) v = to_sym(to_f64(A[(int64_t)grow * lda + kk]), mod);
+            ra[e] = v;
+        }
+        const int kb = k0 + bk;
+#pragma unroll
+        for (int e = 0; e < ELB; ++e) {
+            const int gc = col0 + bc + e;
+            double v = 0.0;
+            if (kb < K && gc < N) v = to_sym(to_f64(B[(int64_t)kb * ldb + gc]), mod);
+            rb[e] = v;
+        }
+    };
+
+    int kacc = 0;
+    if (steps > 0) load_step(0);
+    for (int s = 0; s < steps; ++s) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < ELA; ++e) As[ak + e][ar] = ra[e];
+#pragma unroll
+        for (int e = 0; e < ELB; ++e) Bs[bk][bc + e] = rb[e];
+        __syncthreads();
+        if (s + 1 < steps) load_step(s + 1);
+        if (kacc + BK > args.kchunk) {
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[i][j][v] = mod_reduce(acc[i][j][v], mod);
+            kacc = 0;
+        }
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int kr = ks * 4 + (lane >> 4);
+            double a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = As[kr][wm0 + i * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = Bs[kr][wn0 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        kacc += BK;
+    }
+
+    // Epilogue: C <- (C - acc) mod p.  For v_mfma_f64_16x16x4_f64 the lane
+    // holds rows lane/16 + 4v of its block, column lane%16.
+    T *C = (T *)P.C;
+    bool nz = false;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = row0 + wm0 + i * 16 + (lane >> 4) + 4 * v;
+                const int gc = col0 + wn0 + j * 16 + (lane & 15);
+                if (gr < M && gc < N) {
+                    T *cp = C + (int64_t)gr * P.ldc + gc;
+                    const double x = mod_reduce(to_f64(*cp) - acc[i][j][v], mod);
+                    *cp = from_f64<T>(x);
+                    nz |= (x != 0.0);
+                }
+            }
+    if (nz && P.nzflag) *P.nzflag = P.nzgen;
+}
+
+template <typename T, int BM, int BN>
+static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
+    hipLaunchKernelGGL((modmm_f64_kernel<T, BM, BN>), dim3(total), dim3(256), 0, st, args);
+    return hipGetLastError();
+}
+
+hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
+                            hipStream_t st) {
+    MMArgs args;
+    int n = 0;
+    int64_t tiles128 = 0;
+    for (int q = 0; q < nprob; ++q) {
+        if (probs[q].M <= 0 || probs[q].N <= 0) continue;
+        args.prob[n++] = probs[q];
+        tiles128 += cdiv64(probs[q].M, 128) * cdiv64(probs[q].N, 128);
+    }
+    if (n == 0) return hipSuccess;
+    // Large updates use 128 x 128 tiles; smaller ones 64 x 64 to keep the
+    // 256 compute units busy.
+    const int big = tiles128 >= 240 ? 128 : 64;
+    int total = 0;
+    for (int q = 0; q < n; ++q) {
+        MMProblem &pb = args.prob[q];
+        pb.tileStart = total;
+        pb.tilesN = (int)cdiv64(pb.N, big);
+        total += (int)(cdiv64(pb.M, big) * pb.tilesN);
+        if (pb.K[0] <= 0) { pb.K[0] = 0; }
+        if (pb.K[1] <= 0) { pb.K[1] = 0; }
+    }
+    args.count = n;
+    args.kchunk = kchunk;
+    args.mod.p = p;
+    args.mod.pinv = 1.0 / p;
+    args.mod.half = (double)((int64_t)p / 2);
+    switch (dtype) {
+    case DT_I64:
+        return big == 128 ? launch_t<int64_t, 128, 128>(args, total, st) : launch_t<int64_t, 64, 64>(args, total, st);
+    case DT_F64:
+        return big == 128 ? launch_t<double, 128, 128>(args, total, st) : launch_t<double, 64, 64>(args, total, st);
+    case DT_I32:
+        return big == 128 ? launch_t<int32_t, 128, 128>(args, total, st) : launch_t<int32_t, 64, 64>(args, total, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pluq

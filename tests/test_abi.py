@@ -1,0 +1,67 @@
+"""The C ABI library: it loads, exports every function declared in
+include/pluq.h, and rejects invalid arguments before touching the device
+(no GPU needed: these calls return before any HIP call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1301_4438_amd as pl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pluq.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pluq_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pl.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    for s in range(8):
+        assert pl.pluq_status_string(s) == pl.STATUS[s]
+
+
+def _call(m, n, lda, dt, p, opts=None, work_bytes=1 << 30, r=True):
+    L = pl.load()
+    rr = ctypes.c_int64(-1)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    return L.pluq_modp(m, n, fake, lda, dt, p, fake, fake, ctypes.byref(rr) if r else None,
+                       ctypes.byref(opts) if opts else None, fake, work_bytes, None)
+
+
+def test_argument_errors():
+    assert _call(-1, 5, 5, 1, 7) == 1
+    assert _call(5, 5, 4, 1, 7) == 1            # lda < n
+    assert _call(5, 5, 5, 9, 7) == 1            # bad dtype
+    assert _call(5, 5, 5, 1, 1) == 2            # p < 2
+    assert _call(5, 5, 5, 1, 1 << 26) == 2      # p too large
+    assert _call(5, 5, 5, 1, 7, work_bytes=16) == 7
+    assert _call(5, 5, 5, 1, 7, r=False) == 1
+    bad = pl._opts("fp64", trsm_leaf=65)
+    assert _call(5, 5, 5, 1, 7, opts=bad) == 1
+
+
+def test_workspace_size_monotone():
+    a = pl.pluq_workspace_size(100, 100, 1, 65521)
+    b = pl.pluq_workspace_size(1000, 1000, 1, 65521)
+    assert 0 < a < b
+    assert pl.pluq_workspace_size(-1, 3, 1, 65521) == 0
+
+
+def test_rank_profile_queries_host():
+    P = [2, 0, 1, 3, 4, 5]
+    Q = [0, 1]
+    rr, cc = pl.pluq_rank_profiles(P, Q, 2)
+    assert rr.tolist() == [0, 2] and cc.tolist() == [0, 1]
+    rows, cols = pl.pluq_leading_rank_profiles(P, Q, 2, 2, 2)
+    assert rows.tolist() == [0] and cols.tolist() == [1]
