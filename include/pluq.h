@@ -82,7 +82,7 @@ typedef enum { PLUQ_FORM_FP64 = 0, PLUQ_FORM_INT8 = 1, PLUQ_FORM_FP32 = 2 } pluq
 typedef struct {
     int32_t form;             /* pluq_form */
     int32_t validate_entries; /* non-zero: scan A for entries outside [0,p) first */
-    int32_t cutoff_override;  /* > 0: base-case capacity in elements (tuning only) */
+    int32_t cutoff_override;  /* > 0: base-case tiles at most this many rows and columns (tuning only) */
     int32_t trsm_leaf_override; /* > 0: order of the TRSM leaf solves, <= 64 (tuning only) */
 } pluq_opts;
 
@@ -180,8 +180,12 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
  *             upper part are not read), B r x ncols;
  *   side = 1: B <- B U^{-1}, U r x r upper triangular with non-zero diagonal
  *             (its strict lower part is not read), B nrows x r.
- * `other` is ncols (side 0) or nrows (side 1).
+ * `other` is ncols (side 0) or nrows (side 1).  The 64 x 64 diagonal blocks
+ * of the triangle are inverted first (exactly, over the field) and the solve
+ * then runs as matrix-multiply updates; dWork must hold
+ * pluq_trsm_workspace_size(r, dt) bytes, 256-byte aligned.
  */
+size_t pluq_trsm_workspace_size(int64_t r, pluq_dtype dt);
 pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT,
                       int64_t ldt, void *dB, int64_t ldb, pluq_dtype dt, uint64_t p,
                       int32_t form, void *dWork, size_t work_bytes, void *stream);

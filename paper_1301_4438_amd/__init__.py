@@ -80,6 +80,8 @@ def load():
     L.pluq_modmm.restype = ctypes.c_int
     L.pluq_modmm.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                              ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    L.pluq_trsm_workspace_size.restype = ctypes.c_size_t
+    L.pluq_trsm_workspace_size.argtypes = [_i64, ctypes.c_int]
     L.pluq_trsm.restype = ctypes.c_int
     L.pluq_trsm.argtypes = [ctypes.c_int32, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                             ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
@@ -235,8 +237,9 @@ def pluq_trsm(side: int, T, B, p: int, form="fp64"):
         raise TypeError("T and B must share one element type")
     dt = _dtype_code(B)
     fcode = FORMS[form] if isinstance(form, str) else int(form)
+    work = _workspace(B.device, int(L.pluq_trsm_workspace_size(r, dt)))
     st = L.pluq_trsm(side, r, other, ctypes.c_void_p(T.data_ptr()), T.stride(0), ctypes.c_void_p(B.data_ptr()),
-                     B.stride(0), dt, p, fcode, None, 0, _stream(B))
+                     B.stride(0), dt, p, fcode, ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(B))
     _check(st, "pluq_trsm")
 
 

@@ -79,29 +79,23 @@ bool ensure_pinned(size_t idx_elems, size_t pq_elems) {
 std::once_flag g_bc_once;
 int g_bc_cap = 0;
 
-// Base-case tile capacity: a tile of m*n 32-bit words plus one byte per
-// column must fit the LDS a work-group may use on this device.
+// Base-case tile dimension (rows and columns at most this).
 int bc_cap() {
-    std::call_once(g_bc_once, [] {
-        int dev = 0;
-        size_t lds = 65536;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            lds = prop.sharedMemPerBlock;
-        int64_t cap = bc_capacity();
-        if (bc_init() != hipSuccess) lds = std::min<size_t>(lds, 65536);
-        const int64_t fit = (int64_t)(lds > 1024 ? lds - 1024 : 0) / 5;
-        g_bc_cap = (int)std::max<int64_t>(16, std::min(cap, fit));
-    });
+    std::call_once(g_bc_once, [] { g_bc_cap = (bc_init() == hipSuccess) ? bc_capacity() : 0; });
     return g_bc_cap;
 }
 
 struct Layout {
-    size_t stat_off, idx_off, scratch_off, total;
-    size_t idx_elems, scratch_bytes;
+    size_t stat_off, idx_off, tab_off, w_off, scratch_off, total;
+    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes;
 };
 
-Layout layout(int64_t m, int64_t n, size_t esz) {
+// Diagonal-block inverses of a triangle of order r (TRSM).
+size_t trsm_w_bytes(int64_t r, size_t esz) {
+    return (size_t)((r + TRSM_NB - 1) / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
+}
+
+Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p) {
     Layout L;
     L.idx_elems = (size_t)(4 * (m + n) + 65536);
     const size_t full = (size_t)m * (size_t)n * esz;
@@ -110,7 +104,11 @@ Layout layout(int64_t m, int64_t n, size_t esz) {
     if (L.scratch_bytes == 0) L.scratch_bytes = ALIGN;
     L.stat_off = 0;
     L.idx_off = align_up(STAT_WORDS * sizeof(int32_t));
-    L.scratch_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
+    L.tab_bytes = (p <= 65536) ? BC_TABLE_RESERVE : 0;
+    L.tab_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
+    L.w_bytes = trsm_w_bytes(std::min(m, n), esz);
+    L.w_off = L.tab_off + align_up(L.tab_bytes);
+    L.scratch_off = L.w_off + align_up(L.w_bytes);
     L.total = L.scratch_off + align_up(L.scratch_bytes);
     return L;
 }
@@ -154,7 +152,7 @@ const char *pluq_version(void) { return "pluq-mi355x 0.1 (gfx950)"; }
 
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
-    return layout(m, n, esize(dt)).total;
+    return layout(m, n, esize(dt), p).total;
 }
 
 pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
@@ -168,7 +166,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
     const int form = opts ? opts->form : PLUQ_FORM_FP64;
     if ((s = form_check(form, p)) != PLUQ_OK) return s;
     const size_t esz = esize(dt);
-    const Layout L = layout(m, n, esz);
+    const Layout L = layout(m, n, esz, p);
     if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
     if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
 
@@ -183,6 +181,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.kchunk = (int)std::min<int64_t>(fp64_kchunk(p), 1 << 30);
         c.leaf_nb = (opts && opts->trsm_leaf_override > 0) ? opts->trsm_leaf_override : 64;
         c.cap = bc_cap();
+        if (c.cap <= 0) return PLUQ_ERR_DEVICE;
         if (opts && opts->cutoff_override > 0) c.cap = std::min<int64_t>(c.cap, opts->cutoff_override);
         c.A = (char *)dA;
         c.lda = lda;
@@ -193,8 +192,14 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.idx_cap = L.idx_elems;
         c.scratch = w + L.scratch_off;
         c.scratch_bytes = L.scratch_bytes;
+        c.trsm_w = w + L.w_off;
         c.h_idx = g_pin.idx;
         c.h_stat = g_pin.stat;
+        if (L.tab_bytes && bc_table_bytes((double)p) && m > 0 && n > 0) {
+            c.inv_table = (uint16_t *)(w + L.tab_off);
+            c.cap = std::min<int64_t>(c.cap, bc_tile_limit((double)p));
+            c.launch(K_SCAN, 0, (double)L.tab_bytes, [&] { return launch_build_inv_table(c.inv_table, (double)p, c.st); });
+        }
 
         std::vector<int32_t> prow, pcol;
         int64_t r = 0;
@@ -317,9 +322,13 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, c
     return e == hipSuccess ? PLUQ_OK : PLUQ_ERR_DEVICE;
 }
 
+size_t pluq_trsm_workspace_size(int64_t r, pluq_dtype dt) {
+    if (r < 0 || esize(dt) == 0) return 0;
+    return std::max<size_t>(ALIGN, trsm_w_bytes(r, esize(dt)));
+}
+
 pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT, int64_t ldt, void *dB, int64_t ldb,
                       pluq_dtype dt, uint64_t p, int32_t form, void *dWork, size_t work_bytes, void *stream) {
-    (void)dWork; (void)work_bytes;
     if ((side != 0 && side != 1) || r < 0 || other < 0 || r > INT32_MAX || other > INT32_MAX) return PLUQ_ERR_ARG;
     if (esize(dt) == 0) return PLUQ_ERR_ARG;
     if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
@@ -329,9 +338,8 @@ pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT, in
     if (!dT || !dB || ldt < r) return PLUQ_ERR_ARG;
     if (side == 0 && ldb < other) return PLUQ_ERR_ARG;
     if (side == 1 && ldb < r) return PLUQ_ERR_ARG;
-    // The triangle and B are separate buffers here; run the recursive
-    // solve of the driver with a context whose "matrix" is addressed by
-    // absolute pointers: use two contexts' worth of arithmetic on offsets.
+    if (!dWork || work_bytes < trsm_w_bytes(r, esize(dt))) return PLUQ_ERR_WORKSPACE;
+    if ((uintptr_t)dWork % ALIGN) return PLUQ_ERR_ARG;
     try {
         Ctx c;
         c.dt = (int)dt;
@@ -339,44 +347,12 @@ pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT, in
         c.p = p;
         c.form = form;
         c.kchunk = (int)fp64_kchunk(p);
-        c.leaf_nb = 64;
         c.st = (hipStream_t)stream;
-        // Address both operands relative to the lower of the two pointers
-        // with a common leading dimension is not possible in general, so
-        // solve blockwise here with explicit pointers.
-        const char *T = (const char *)dT;
-        char *B = (char *)dB;
-        const size_t esz = c.esz;
-        auto Tp = [&](int64_t i, int64_t j) { return (const void *)(T + ((size_t)i * ldt + j) * esz); };
-        auto Bp = [&](int64_t i, int64_t j) { return (void *)(B + ((size_t)i * ldb + j) * esz); };
-        const int64_t nb = 64;
-        if (side == 0) {
-            // blocked forward substitution: B_i <- L_ii^{-1} (B_i - sum_{j<i} L_ij B_j)
-            for (int64_t i0 = 0; i0 < r; i0 += nb) {
-                const int64_t bi = std::min(nb, r - i0);
-                if (i0 > 0) {
-                    MMProblem pb;
-                    std::memset(&pb, 0, sizeof(pb));
-                    pb.C = Bp(i0, 0); pb.ldc = ldb; pb.M = (int32_t)bi; pb.N = (int32_t)other;
-                    pb.A[0] = Tp(i0, 0); pb.lda[0] = ldt; pb.B[0] = Bp(0, 0); pb.ldb[0] = ldb; pb.K[0] = (int32_t)i0;
-                    c.check(launch_modmm_f64(c.dt, &pb, 1, (double)p, c.kchunk, c.st));
-                }
-                c.check(launch_trsm_llu_leaf(c.dt, Tp(i0, i0), ldt, (int)bi, Bp(i0, 0), ldb, other, (double)p, c.kchunk, c.st));
-            }
-        } else {
-            // blocked: B_:j <- (B_:j - sum_{i<j} B_:i U_ij) U_jj^{-1}
-            for (int64_t j0 = 0; j0 < r; j0 += nb) {
-                const int64_t bj = std::min(nb, r - j0);
-                if (j0 > 0) {
-                    MMProblem pb;
-                    std::memset(&pb, 0, sizeof(pb));
-                    pb.C = Bp(0, j0); pb.ldc = ldb; pb.M = (int32_t)other; pb.N = (int32_t)bj;
-                    pb.A[0] = Bp(0, 0); pb.lda[0] = ldb; pb.B[0] = Tp(0, j0); pb.ldb[0] = ldt; pb.K[0] = (int32_t)j0;
-                    c.check(launch_modmm_f64(c.dt, &pb, 1, (double)p, c.kchunk, c.st));
-                }
-                c.check(launch_trsm_run_leaf(c.dt, Bp(0, j0), ldb, other, Tp(j0, j0), ldt, (int)bj, (double)p, c.kchunk, c.st));
-            }
-        }
+        c.trsm_w = (char *)dWork;
+        if (side == 0)
+            c.trsm_llu_p((const char *)dT, ldt, r, (char *)dB, ldb, other);
+        else
+            c.trsm_run_p((char *)dB, ldb, other, (const char *)dT, ldt, r);
     } catch (const DeviceError &) {
         return PLUQ_ERR_DEVICE;
     }

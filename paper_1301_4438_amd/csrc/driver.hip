@@ -29,6 +29,7 @@ namespace pluq {
 
 thread_local Stats g_last_stats;
 thread_local Profiler g_prof;
+thread_local LaunchEvents g_launch_events;
 
 hipError_t Profiler::begin(hipStream_t st, size_t *idx) {
     while (pool.size() < used + 2) {
@@ -37,14 +38,19 @@ hipError_t Profiler::begin(hipStream_t st, size_t *idx) {
         if (err != hipSuccess) return err;
         pool.push_back(e);
     }
+    (void)st;
     *idx = used;
     used += 2;
-    return hipEventRecord(pool[*idx], st);
+    g_launch_events.start = pool[*idx];
+    g_launch_events.stop = pool[*idx + 1];
+    return hipSuccess;
 }
 
 hipError_t Profiler::end(hipStream_t st, size_t idx, int cls, double flops, double bytes) {
+    (void)st;
+    g_launch_events = LaunchEvents();
     pending.push_back({cls, idx, flops, bytes});
-    return hipEventRecord(pool[idx + 1], st);
+    return hipSuccess;
 }
 
 void Profiler::resolve() {
@@ -196,42 +202,69 @@ static void mmpair(MMProblem &pb, int s, const void *A, int64_t lda, const void 
 
 // ------------------------------------------------------------------ TRSM --
 
+// Split of a triangle of order r > 64: a multiple of 64 near r/2, so that
+// the leaves are exactly the 64 x 64 diagonal blocks inverted up front.
 static int64_t trsm_split(int64_t r) {
-    int64_t h = r / 2;
-    if (h >= 64) h -= h % 64;
-    return h;
+    const int64_t h = (r / 2) - (r / 2) % TRSM_NB;
+    return h < TRSM_NB ? TRSM_NB : h;
 }
 
-// B (r x ncols at (bi, bj)) <- L^{-1} B, L unit lower r x r at (li, lj).
-void Ctx::trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols) {
+// TRSM(L, B) of Section 2: B (r x ncols, ldb) <- L^{-1} B, L unit lower r x r.
+// The diagonal blocks are inverted in one launch; the recursion then runs on
+// the matrix cores only: two half solves around an MM update, and at a leaf
+// the in-place product B_q <- B_q - (I - L_qq^{-1}) B_q.
+void Ctx::trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols) {
     if (r <= 0 || ncols <= 0) return;
-    if (r <= leaf_nb) {
-        launch(K_TRSM, 0, (2.0 * r * ncols + r * r) * esz,
-               [&] { return launch_trsm_llu_leaf(dt, at(li, lj), lda, (int)r, at(bi, bj), lda, ncols, (double)p, kchunk, st); });
-        return;
-    }
-    const int64_t r1 = trsm_split(r);
-    trsm_llu(li, lj, r1, bi, bj, ncols);
-    MMProblem pb = mmprob(at(bi + r1, bj), lda, r - r1, ncols);
-    mmpair(pb, 0, at(li + r1, lj), lda, at(bi, bj), lda, r1);
-    mm(&pb, 1);
-    trsm_llu(li + r1, lj + r1, r - r1, bi + r1, bj, ncols);
+    launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 2,
+           [&] { return launch_trsm_diag_inv(dt, 0, L, ldl, r, trsm_w, (double)p, kchunk, st); });
+    trsm_llu_rec(L, ldl, r, B, ldb, ncols, 0);
 }
 
-// B (nrows x r at (bi, bj)) <- B U^{-1}, U upper r x r at (ui, uj).
-void Ctx::trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r) {
-    if (r <= 0 || nrows <= 0) return;
-    if (r <= leaf_nb) {
-        launch(K_TRSM, 0, (2.0 * r * nrows + r * r) * esz,
-               [&] { return launch_trsm_run_leaf(dt, at(bi, bj), lda, nrows, at(ui, uj), lda, (int)r, (double)p, kchunk, st); });
+void Ctx::trsm_llu_rec(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols, int64_t off) {
+    if (r <= TRSM_NB) {
+        MMProblem pb = mmprob(B, ldb, r, ncols);
+        mmpair(pb, 0, trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz, TRSM_NB, B, ldb, r);
+        mm(&pb, 1);
         return;
     }
     const int64_t r1 = trsm_split(r);
-    trsm_run(bi, bj, nrows, ui, uj, r1);
-    MMProblem pb = mmprob(at(bi, bj + r1), lda, nrows, r - r1);
-    mmpair(pb, 0, at(bi, bj), lda, at(ui, uj + r1), lda, r1);
+    trsm_llu_rec(L, ldl, r1, B, ldb, ncols, off);
+    MMProblem pb = mmprob(B + (size_t)r1 * ldb * esz, ldb, r - r1, ncols);
+    mmpair(pb, 0, L + (size_t)r1 * ldl * esz, ldl, B, ldb, r1);
     mm(&pb, 1);
-    trsm_run(bi, bj + r1, nrows, ui + r1, uj + r1, r - r1);
+    trsm_llu_rec(L + ((size_t)r1 * ldl + r1) * esz, ldl, r - r1, B + (size_t)r1 * ldb * esz, ldb, ncols, off + r1);
+}
+
+// TRSM(B, U) of Section 2: B (nrows x r, ldb) <- B U^{-1}, U upper r x r
+// with non-zero diagonal; same scheme, leaf B_q <- B_q - B_q (I - U_qq^{-1}).
+void Ctx::trsm_run_p(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r) {
+    if (r <= 0 || nrows <= 0) return;
+    launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 2,
+           [&] { return launch_trsm_diag_inv(dt, 1, U, ldu, r, trsm_w, (double)p, kchunk, st); });
+    trsm_run_rec(B, ldb, nrows, U, ldu, r, 0);
+}
+
+void Ctx::trsm_run_rec(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r, int64_t off) {
+    if (r <= TRSM_NB) {
+        MMProblem pb = mmprob(B, ldb, nrows, r);
+        mmpair(pb, 0, B, ldb, trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz, TRSM_NB, r);
+        mm(&pb, 1);
+        return;
+    }
+    const int64_t r1 = trsm_split(r);
+    trsm_run_rec(B, ldb, nrows, U, ldu, r1, off);
+    MMProblem pb = mmprob(B + (size_t)r1 * esz, ldb, nrows, r - r1);
+    mmpair(pb, 0, B, ldb, U + (size_t)r1 * esz, ldu, r1);
+    mm(&pb, 1);
+    trsm_run_rec(B + (size_t)r1 * esz, ldb, nrows, U + ((size_t)r1 * ldu + r1) * esz, ldu, r - r1, off + r1);
+}
+
+void Ctx::trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols) {
+    trsm_llu_p(at(li, lj), lda, r, at(bi, bj), lda, ncols);
+}
+
+void Ctx::trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r) {
+    trsm_run_p(at(bi, bj), lda, nrows, at(ui, uj), lda, r);
 }
 
 // ------------------------------------------------------------- base case --
@@ -312,7 +345,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     // optimistic: the identity order (generic rank profile)
     const double tbytes = 2.0 * m * n * esz;
     launch(K_BASE, 0, tbytes, [&] {
-        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, d_stat + STAT_BC, st);
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table, d_stat + STAT_BC, st);
     });
     read_status(STAT_BC, 2);
     if (h_stat[STAT_BC + 1] == 1) {
@@ -322,7 +355,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     }
     // general: rank profile matrix, then the pivot order, then the ordered LU
     launch(K_BASE, 0, 1.0 * m * n * esz,
-           [&] { return launch_bc_rpm(dt, at(gi, gj), lda, (int)m, (int)n, (double)p, d_stat + STAT_BC, st); });
+           [&] { return launch_bc_rpm(dt, at(gi, gj), lda, (int)m, (int)n, (double)p, kchunk, d_stat + STAT_BC, st); });
     read_status(STAT_BC, 1 + m);
     const int64_t r = h_stat[STAT_BC];
     for (int64_t i = 0; i < m; ++i)
@@ -334,7 +367,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     const int32_t *drow = upload(prow.data(), m);
     const int32_t *dcol = upload(pcol.data(), n);
     launch(K_BASE, 0, tbytes, [&] {
-        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, d_stat + STAT_BC, st);
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table, d_stat + STAT_BC, st);
     });
     return r;
 }
@@ -373,7 +406,7 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
         iota(pcol, n);
         return 0;
     }
-    if (m * n <= cap) return basecase(gi, gj, m, n, prow, pcol);
+    if (m <= cap && n <= cap) return basecase(gi, gj, m, n, prow, pcol);
     if (z == Z_UNKNOWN) {
         Blk b{gi, gj, m, n};
         resolve_zero(1, &b, &z, nullptr);

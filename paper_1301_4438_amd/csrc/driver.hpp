@@ -72,6 +72,8 @@ struct Ctx {
     int32_t *d_idx = nullptr;
     size_t idx_cap = 0, idx_used = 0;
     int32_t *d_stat = nullptr;
+    uint16_t *inv_table = nullptr;   // inverses mod p for the base case (or null)
+    char *trsm_w = nullptr;          // I - T_qq^{-1} blocks of the current solve
     // pinned host mirrors
     int32_t *h_idx = nullptr;
     int32_t *h_stat = nullptr;
@@ -99,6 +101,10 @@ struct Ctx {
     void mm(MMProblem *probs, int n);
     void trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols);
     void trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r);
+    void trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols);
+    void trsm_run_p(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r);
+    void trsm_llu_rec(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols, int64_t off);
+    void trsm_run_rec(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r, int64_t off);
     int64_t basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<int32_t> &prow,
                      std::vector<int32_t> &pcol);
     void resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens);

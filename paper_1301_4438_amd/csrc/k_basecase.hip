@@ -1,5 +1,6 @@
-// Base case of the recursion: the decomposition of a tile small enough to sit
-// in the LDS of one compute unit (m * n <= bc_capacity()).
+// Base case of the recursion: the decomposition of a tile of at most
+// TILE x TILE entries (TILE = 64 or 128), done by one work-group of 256
+// threads.
 //
 // The output must be exactly the one Algorithm 1 would produce on the tile
 // (pivots in the order of its four recursive calls, non-pivot rows and
@@ -10,8 +11,7 @@
 //              pivot is the first non-zero entry of the reduced row (the
 //              row-major search of the row-rank-profile eliminations recalled
 //              in Section 1; the reduced row's first non-zero column is where
-//              the rank of the leading sub-matrices jumps).  The pivot of row
-//              i is found with a wavefront ballot and find-first-set.
+//              the rank of the leading sub-matrices jumps);
 //   bc_lu   -- elimination without pivoting of the tile gathered through the
 //              row/column order, written back in packed form.
 // bc_lu is also tried first on the tile as it is: when every pivot on the
@@ -20,65 +20,210 @@
 // zero pivot appears, the identity order is already the right one and the
 // rank-profile pass is skipped.  The pivot order itself is computed on the
 // host between the two kernels (index bookkeeping only).
+//
+// Layout: thread (ty, tx) = (tid / 16, tid % 16) holds the R x R entries
+// (ty + 16a, tx + 16b), R = TILE / 16, in registers, so the shrinking trailing
+// block stays evenly spread over the threads.  Register indices that depend
+// on the step are resolved by a wave-uniform switch, never by indexing.
+// Pivot inverses come from an LDS table of inverses when p <= 65536 (then
+// tiles are at most 64 x 64 so that table and output tile share the LDS),
+// else from the extended Euclidean algorithm.
+// Arithmetic uses delayed reduction (Section 6) inside the elimination: the
+// update is one FMA of symmetric residues on an exact integer-valued double,
+// an entry is reduced when it joins a pivot row or column, and every entry is
+// reduced after `kchunk` steps so that no accumulator exceeds 2^52.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace pluq {
 
 constexpr int BC_THREADS = 256;
-constexpr int BC_CAP = 16384;                  // elements (u32) of a tile
-constexpr int BC_LDS = BC_CAP * 4 + 16384 + 64; // tile + per-column flags + slack
+constexpr int BC_DIM = 128;            // largest tile
+constexpr int BC_TAB_MAX = 65536;      // largest p with an LDS inverse table
+constexpr size_t BC_TAB_BYTES = BC_TAB_MAX * sizeof(uint16_t);
 
-template <typename T>
+// Inverse of every non-zero residue mod p (p <= 65536), as uint16.
+__global__ __launch_bounds__(256) void build_inv_table_kernel(uint16_t *tab, ModP mod) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    const int p = (int)mod.p;
+    if (a < p) tab[a] = (uint16_t)(a == 0 ? 0 : (int)mod_inv((double)a, mod));
+}
+
+// bc_lu step structure (one step = one pivot s):
+//   P1  every thread finalises one entry of the pivot row or column:
+//       reads its raw value from LDS, reduces it, writes the final U (row) or
+//       L (column) value to the LDS output tile and publishes the symmetric
+//       residue used by the update (the multipliers are the column scaled by
+//       the pivot's inverse, which each thread looks up itself);
+//   P2  every thread applies the rank-one update to its registers with
+//       branch-free FMAs (inactive rows and columns were published as zero),
+//       and the owners of row and column s+1 copy them to LDS for the next P1.
+// Two barriers per step; the output tile is copied to global memory only on
+// success, so a failed optimistic attempt leaves the input untouched.
+struct BcShared {
+    double row[BC_DIM];   // raw entries of the next pivot row
+    double col[BC_DIM];   // raw entries of the next pivot column
+    double Lb[BC_DIM];    // published multipliers (symmetric)
+    double Ub[BC_DIM];    // published pivot row (symmetric)
+};
+
+__device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const uint16_t *tab) {
+    if (x == 0.0) return 0.0;
+    return tab ? (double)tab[(int)x] : mod_inv(x, mod);
+}
+
+// OUT is the output tile's word type: uint16_t when residues fit (p <= 65536),
+// uint32_t otherwise.
+template <typename T, int TILE, typename OUT>
 __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, int m, int n,
-                                                           const int32_t *rmap,
-                                                           const int32_t *cmap, int r_known,
-                                                           ModP mod, int32_t *status) {
-    extern __shared__ uint32_t S[];
-    __shared__ double s_inv;
-    __shared__ int s_zero;
+                                                           const int32_t *rmap, const int32_t *cmap,
+                                                           int r_known, ModP mod, int kchunk,
+                                                           const uint16_t *gtab, int32_t *status) {
+    constexpr int R = TILE / 16;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    __shared__ BcShared sh;
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < m * n; idx += BC_THREADS) {
-        const int i = idx / n, j = idx % n;
-        const int64_t gi = rmap ? rmap[i] : i;
-        const int64_t gj = cmap ? cmap[j] : j;
-        S[idx] = (uint32_t)to_f64(A[gi * lda + gj]);
+    const int ty = tid >> 4, tx = tid & 15;
+    OUT *out = (OUT *)dyn;                                   // TILE x TILE
+    const uint16_t *tab = nullptr;
+    constexpr size_t OUT_BYTES = (size_t)TILE * TILE * sizeof(OUT);
+
+    // zero the output tile; copy the inverse table (16-byte words, in flight together)
+    {
+        uint4 *o4 = (uint4 *)dyn;
+        constexpr int OW = (int)(OUT_BYTES / 16);
+#pragma unroll
+        for (int k = 0; k < (OW + BC_THREADS - 1) / BC_THREADS; ++k) {
+            const int w = tid + k * BC_THREADS;
+            if (w < OW) o4[w] = make_uint4(0, 0, 0, 0);
+        }
+    }
+    if (gtab) {
+        const int words = ((int)mod.p + 7) / 8;
+        const uint4 *src = (const uint4 *)gtab;
+        uint4 *dst = (uint4 *)(dyn + OUT_BYTES);
+        constexpr int PER = BC_TAB_MAX / 8 / BC_THREADS;   // 16-byte words per thread
+        constexpr int CH = 8;                               // loads in flight per thread
+#pragma unroll
+        for (int k0 = 0; k0 < PER; k0 += CH) {
+            uint4 tmp[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int w = tid + (k0 + k) * BC_THREADS;
+                tmp[k] = (w < words) ? src[w] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int w = tid + (k0 + k) * BC_THREADS;
+                if (w < words) dst[w] = tmp[k];
+            }
+        }
+        tab = (const uint16_t *)(dyn + OUT_BYTES);
+    }
+
+    double v[R][R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+        const int i = ty + 16 * a;
+        const int64_t gi = (i < m) ? (rmap ? rmap[i] : i) : 0;
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            const int j = tx + 16 * b;
+            double x = 0.0;
+            if (i < m && j < n) x = to_f64(A[gi * lda + (cmap ? cmap[j] : j)]);
+            v[a][b] = x;
+        }
+    }
+    if (ty == 0) {
+#pragma unroll
+        for (int b = 0; b < R; ++b) sh.row[tx + 16 * b] = v[0][b];
+    }
+    if (tx == 0) {
+#pragma unroll
+        for (int a = 0; a < R; ++a) sh.col[ty + 16 * a] = v[a][0];
     }
     __syncthreads();
+
     const int kmax = m < n ? m : n;
     const int steps = r_known >= 0 ? r_known : kmax;
     int r = steps;
     bool ok = true;
+    int since = 0;
     for (int s = 0; s < steps; ++s) {
-        if (tid == 0) {
-            const double v = (double)S[s * n + s];
-            s_zero = (v == 0.0);
-            if (v != 0.0) s_inv = mod_inv(v, mod);
-        }
-        __syncthreads();
-        if (s_zero) {
-            // zero pivot: the identity order is right iff the rest is zero
+        // ---- P1
+        const double piv = mod_reduce(sh.row[s], mod);
+        if (piv == 0.0) {
+            // zero pivot at (s, s): the identity order is right iff the rest is zero
             int any = 0;
-            const int w = n - s;
-            for (int idx = tid; idx < (m - s) * w; idx += BC_THREADS)
-                any |= (S[(s + idx / w) * n + s + idx % w] != 0u);
+#pragma unroll
+            for (int a = 0; a < R; ++a)
+#pragma unroll
+                for (int b = 0; b < R; ++b) {
+                    const int i = ty + 16 * a, j = tx + 16 * b;
+                    if (i >= s && j >= s && i < m && j < n) any |= (mod_reduce(v[a][b], mod) != 0.0);
+                }
             any = __syncthreads_or(any);
-            ok = (any == 0);
+            ok = (any == 0) && (r_known < 0);
             r = s;
             break;
         }
-        const double inv = s_inv;
-        for (int i = s + 1 + tid; i < m; i += BC_THREADS)
-            S[i * n + s] = (uint32_t)mod_mul((double)S[i * n + s], inv, mod);
+        const double inv = bc_inverse(piv, mod, tab);
+        if (tid < TILE) {
+            const int j = tid;
+            const double u = mod_reduce(sh.row[j], mod);
+            const bool act = (j < n);
+            if (act && j >= s) out[s * TILE + j] = (OUT)u;
+            sh.Ub[j] = (act && j > s) ? to_sym(u, mod) : 0.0;
+        } else if (tid < 2 * TILE) {
+            const int i = tid - TILE;
+            const bool act = (i > s) && (i < m);
+            const double l = mod_mul(mod_reduce(sh.col[i], mod), inv, mod);
+            if (act) out[i * TILE + s] = (OUT)l;
+            sh.Lb[i] = act ? to_sym(l, mod) : 0.0;
+        }
         __syncthreads();
-        const int w = n - s - 1;
-        const int cnt = (m - s - 1) * w;
-        for (int idx = tid; idx < cnt; idx += BC_THREADS) {
-            const int i = s + 1 + idx / w, j = s + 1 + idx % w;
-            const uint32_t l = S[i * n + s];
-            const uint32_t u = S[s * n + j];
-            if (l != 0u && u != 0u)
-                S[i * n + j] = (uint32_t)mod_reduce((double)S[i * n + j] - (double)l * (double)u, mod);
+        // ---- P2
+        double l[R], u[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) l[a] = sh.Lb[ty + 16 * a];
+#pragma unroll
+        for (int b = 0; b < R; ++b) u[b] = sh.Ub[tx + 16 * b];
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
+        if (++since >= kchunk) {
+            since = 0;
+#pragma unroll
+            for (int a = 0; a < R; ++a)
+#pragma unroll
+                for (int b = 0; b < R; ++b) v[a][b] = mod_reduce(v[a][b], mod);
+        }
+        if (s + 1 < steps) {
+            // owners of row / column s+1 copy them to LDS; the register index
+            // (s+1)/16 is wave-uniform and resolved by the switch
+            const int t = s + 1;
+#define PLUQ_BC_PUB(Q)                                                                      \
+    if constexpr ((Q) < R) {                                                                \
+        if (ty == (t & 15)) {                                                               \
+            _Pragma("unroll") for (int b = 0; b < R; ++b) sh.row[tx + 16 * b] = v[(Q)][b];  \
+        }                                                                                   \
+        if (tx == (t & 15)) {                                                               \
+            _Pragma("unroll") for (int a = 0; a < R; ++a) sh.col[ty + 16 * a] = v[a][(Q)];  \
+        }                                                                                   \
+    }
+            switch (t >> 4) {
+            case 0: PLUQ_BC_PUB(0) break;
+            case 1: PLUQ_BC_PUB(1) break;
+            case 2: PLUQ_BC_PUB(2) break;
+            case 3: PLUQ_BC_PUB(3) break;
+            case 4: PLUQ_BC_PUB(4) break;
+            case 5: PLUQ_BC_PUB(5) break;
+            case 6: PLUQ_BC_PUB(6) break;
+            case 7: PLUQ_BC_PUB(7) break;
+            default: break;
+            }
+#undef PLUQ_BC_PUB
         }
         __syncthreads();
     }
@@ -86,64 +231,121 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         if (tid == 0) { status[0] = r; status[1] = 0; }
         return;
     }
-    for (int idx = tid; idx < m * n; idx += BC_THREADS) {
-        const int i = idx / n, j = idx % n;
-        A[(int64_t)i * lda + j] = from_f64<T>((double)S[idx]);
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+        const int i = ty + 16 * a;
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            const int j = tx + 16 * b;
+            if (i < m && j < n) A[(int64_t)i * lda + j] = from_f64<T>((double)out[i * TILE + j]);
+        }
     }
     if (tid == 0) { status[0] = r; status[1] = 1; }
 }
 
+// Rank profile matrix of the tile: status[0] = r, status[1 + i] = pivot
+// column of row i or -1.  Rows are processed in order; the pivot of row i is
+// the first non-zero entry of the reduced row among the columns that are not
+// yet pivot columns.  (Taken for non-generic tiles only.)
 template <typename T>
 __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t lda, int m, int n,
-                                                            ModP mod, int32_t *status) {
-    extern __shared__ uint32_t S[];
-    uint8_t *dead = (uint8_t *)(S + m * n);
-    __shared__ int s_col[2];
-    __shared__ double s_inv[2];
+                                                            ModP mod, int kchunk, int32_t *status) {
+    constexpr int R = 8;
+    __shared__ double Lb[BC_DIM];
+    __shared__ double Ub[2][BC_DIM];
+    __shared__ int mins[2][16];
+    __shared__ double s_inv;
+    __shared__ unsigned char dead[BC_DIM];
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    for (int idx = tid; idx < m * n; idx += BC_THREADS)
-        S[idx] = (uint32_t)to_f64(A[(int64_t)(idx / n) * lda + idx % n]);
-    for (int j = tid; j < n; j += BC_THREADS) dead[j] = 0;
+    const int ty = tid >> 4, tx = tid & 15;
+    double v[R][R];
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+            const int i = ty + 16 * a, j = tx + 16 * b;
+            v[a][b] = (i < m && j < n) ? to_f64(A[(int64_t)i * lda + j]) : 0.0;
+        }
+    if (tid < BC_DIM) dead[tid] = 0;
+    if (tid < m) status[1 + tid] = -1;
     __syncthreads();
-    int r = 0;
+    int r = 0, since = 0;
     for (int i = 0; i < m; ++i) {
         const int buf = i & 1;
-        if (tid < 64) {
-            int found = -1;
-            for (int c0 = 0; c0 < n; c0 += 64) {
-                const int c = c0 + lane;
-                const bool nz = (c < n) && S[i * n + c] != 0u && !dead[c];
-                const unsigned long long mask = __ballot(nz);
-                if (mask) { found = c0 + __ffsll((long long)mask) - 1; break; }
+        const int ai = i >> 4;
+        if (ty == (i & 15)) {
+            int first = 1 << 30;
+#pragma unroll
+            for (int b = 0; b < R; ++b) {
+                const int j = tx + 16 * b;
+                if (j < n && !dead[j]) {
+#pragma unroll
+                    for (int a = 0; a < R; ++a)
+                        if (a == ai) {
+                            const double u = mod_reduce(v[a][b], mod);
+                            v[a][b] = u;
+                            Ub[buf][j] = to_sym(u, mod);
+                            if (u != 0.0 && j < first) first = j;
+                        }
+                }
             }
-            if (lane == 0) {
-                s_col[buf] = found;
-                status[1 + i] = found;
-                if (found >= 0) {
-                    s_inv[buf] = mod_inv((double)S[i * n + found], mod);
-                    dead[found] = 1;
+            mins[buf][tx] = first;
+        }
+        __syncthreads();
+        int jc = 1 << 30;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) jc = min(jc, mins[buf][t]);
+        if (jc >= n) continue;   // dependent row (uniform)
+        ++r;
+        if (ty == (i & 15) && tx == (jc & 15)) {
+            const int bj = jc >> 4;
+#pragma unroll
+            for (int a = 0; a < R; ++a)
+#pragma unroll
+                for (int b = 0; b < R; ++b)
+                    if (a == ai && b == bj) s_inv = mod_inv(v[a][b], mod);
+            dead[jc] = 1;
+            status[1 + i] = jc;
+        }
+        __syncthreads();
+        const double inv = s_inv;
+        if (tx == (jc & 15)) {
+            const int bj = jc >> 4;
+#pragma unroll
+            for (int a = 0; a < R; ++a) {
+                const int k = ty + 16 * a;
+                if (k > i && k < m) {
+#pragma unroll
+                    for (int b = 0; b < R; ++b)
+                        if (b == bj) Lb[k] = to_sym(mod_mul(mod_reduce(v[a][b], mod), inv, mod), mod);
                 }
             }
         }
         __syncthreads();
-        const int jc = s_col[buf];
-        if (jc < 0) continue;
-        ++r;
-        const double inv = s_inv[buf];
-        const int cnt = (m - i - 1) * n;
-        for (int idx = tid; idx < cnt; idx += BC_THREADS) {
-            const int k = i + 1 + idx / n, c = idx % n;
-            if (dead[c]) continue;
-            const uint32_t u = S[i * n + c];
-            if (u == 0u) continue;
-            const uint32_t l = S[k * n + jc];
-            if (l == 0u) continue;
-            const double lm = mod_mul((double)l, inv, mod);
-            S[k * n + c] = (uint32_t)mod_reduce((double)S[k * n + c] - lm * (double)u, mod);
+        ++since;
+        const bool red = since >= kchunk;
+        if (red) since = 0;
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+            const int k = ty + 16 * a;
+            if (k > i && k < m) {
+                const double l = Lb[k];
+#pragma unroll
+                for (int b = 0; b < R; ++b) {
+                    const int j = tx + 16 * b;
+                    if (j < n && !dead[j]) {
+                        double x = fma(-l, Ub[buf][j], v[a][b]);
+                        if (red) x = mod_reduce(x, mod);
+                        v[a][b] = x;
+                    }
+                }
+            }
         }
-        __syncthreads();
+        // Ub is double-buffered: the next row's owners fill the other half
+        // before its first barrier.  Lb, s_inv and dead are rewritten only
+        // after that barrier, which every thread reaches after this update.
     }
+    __syncthreads();
     if (tid == 0) status[0] = r;
 }
 
@@ -155,62 +357,109 @@ static ModP make_mod(double p) {
     return md;
 }
 
-int bc_capacity() { return BC_CAP; }
+static bool g_tab_ok = false;
+
+int bc_capacity() { return BC_DIM; }
+
+// LDS of the tile kernels: the output tile (64 x 64 x 2 B with the table of
+// inverses, 128 x 128 x 2 or 4 B without) plus the 128 KB table when used.
+constexpr size_t BC_LDS_TAB = BC_TAB_BYTES + (size_t)64 * 64 * sizeof(uint16_t);
+constexpr size_t BC_LDS_BIG = (size_t)BC_DIM * BC_DIM * sizeof(uint32_t);
 
 hipError_t bc_init() {
-    hipError_t e;
-#define PLUQ_SETLDS(K)                                                                              \
-    e = hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, BC_LDS); \
-    if (e != hipSuccess) return e;
-    PLUQ_SETLDS(bc_lu_kernel<int64_t>)
-    PLUQ_SETLDS(bc_lu_kernel<double>)
-    PLUQ_SETLDS(bc_lu_kernel<int32_t>)
-    PLUQ_SETLDS(bc_rpm_kernel<int64_t>)
-    PLUQ_SETLDS(bc_rpm_kernel<double>)
-    PLUQ_SETLDS(bc_rpm_kernel<int32_t>)
+    // The LDS inverse table needs a large dynamic LDS allocation; without it
+    // the kernels compute inverses by the extended Euclidean algorithm.
+    g_tab_ok = true;
+#define PLUQ_SETLDS(K, BYTES, FLAG)                                                                         \
+    if (hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BYTES)) != \
+        hipSuccess)                                                                                         \
+        FLAG = false;
+    bool big_ok = true;
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64, uint16_t>), BC_LDS_TAB, g_tab_ok)
+    PLUQ_SETLDS((bc_lu_kernel<double, 64, uint16_t>), BC_LDS_TAB, g_tab_ok)
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64, uint16_t>), BC_LDS_TAB, g_tab_ok)
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, uint16_t>), BC_LDS_BIG, big_ok)
+    PLUQ_SETLDS((bc_lu_kernel<double, 128, uint16_t>), BC_LDS_BIG, big_ok)
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, uint16_t>), BC_LDS_BIG, big_ok)
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, uint32_t>), BC_LDS_BIG, big_ok)
+    PLUQ_SETLDS((bc_lu_kernel<double, 128, uint32_t>), BC_LDS_BIG, big_ok)
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, uint32_t>), BC_LDS_BIG, big_ok)
 #undef PLUQ_SETLDS
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        prop.sharedMemPerBlock < BC_LDS_TAB + sizeof(BcShared) + 1024)
+        g_tab_ok = false;
+    (void)hipGetLastError();
+    (void)big_ok;   // 64 KB of dynamic LDS is available on every CDNA part
     return hipSuccess;
 }
 
-hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
-                        const int32_t *cmap, int r_known, double p, int32_t *status,
-                        hipStream_t st) {
-    if ((int64_t)m * n > BC_CAP || m <= 0 || n <= 0) return hipErrorInvalidValue;
-    const size_t lds = (size_t)m * n * 4;
+int bc_tile_limit(double p) { return (g_tab_ok && p <= BC_TAB_MAX) ? 64 : BC_DIM; }
+
+size_t bc_table_bytes(double p) { return (g_tab_ok && p <= BC_TAB_MAX) ? BC_TAB_BYTES : 0; }
+
+hipError_t launch_build_inv_table(uint16_t *tab, double p, hipStream_t st) {
+    if (p > BC_TAB_MAX) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)(((int64_t)p + 255) / 256);
+    PLUQ_LAUNCH(build_inv_table_kernel, dim3(blocks), dim3(256), 0, st, tab, make_mod(p));
+    return hipGetLastError();
+}
+
+template <int TILE, typename OUT>
+static hipError_t bc_lu_t(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
+                          const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
+                          int32_t *status, hipStream_t st) {
+    const size_t lds = (size_t)TILE * TILE * sizeof(OUT) + (tab ? BC_TAB_BYTES : 0);
+    const ModP md = make_mod(p);
     switch (dtype) {
     case DT_I64:
-        hipLaunchKernelGGL(bc_lu_kernel<int64_t>, dim3(1), dim3(BC_THREADS), lds, st, (int64_t *)A, lda, m, n,
-                           rmap, cmap, r_known, make_mod(p), status);
+        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE, OUT>), dim3(1), dim3(BC_THREADS), lds, st, (int64_t *)A, lda,
+                    m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     case DT_F64:
-        hipLaunchKernelGGL(bc_lu_kernel<double>, dim3(1), dim3(BC_THREADS), lds, st, (double *)A, lda, m, n,
-                           rmap, cmap, r_known, make_mod(p), status);
+        PLUQ_LAUNCH((bc_lu_kernel<double, TILE, OUT>), dim3(1), dim3(BC_THREADS), lds, st, (double *)A, lda,
+                    m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     case DT_I32:
-        hipLaunchKernelGGL(bc_lu_kernel<int32_t>, dim3(1), dim3(BC_THREADS), lds, st, (int32_t *)A, lda, m, n,
-                           rmap, cmap, r_known, make_mod(p), status);
+        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE, OUT>), dim3(1), dim3(BC_THREADS), lds, st, (int32_t *)A, lda,
+                    m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p,
+hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
+                        const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
+                        int32_t *status, hipStream_t st) {
+    if (m > BC_DIM || n > BC_DIM || m <= 0 || n <= 0 || kchunk < 1) return hipErrorInvalidValue;
+    // With the table of inverses only 64 x 64 tiles fit the LDS next to it.
+    // Residues fit 16-bit words exactly when p <= 65536.
+    if (tab) {
+        if (p > BC_TAB_MAX || m > 64 || n > 64) return hipErrorInvalidValue;
+        return bc_lu_t<64, uint16_t>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, st);
+    }
+    if (p <= 65536)
+        return bc_lu_t<128, uint16_t>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, nullptr, status, st);
+    return bc_lu_t<128, uint32_t>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, nullptr, status, st);
+}
+
+hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,
                          int32_t *status, hipStream_t st) {
-    if ((int64_t)m * n > BC_CAP || m <= 0 || n <= 0) return hipErrorInvalidValue;
-    const size_t lds = (size_t)m * n * 4 + (size_t)n + 16;
+    if (m > BC_DIM || n > BC_DIM || m <= 0 || n <= 0 || kchunk < 1) return hipErrorInvalidValue;
     switch (dtype) {
     case DT_I64:
-        hipLaunchKernelGGL(bc_rpm_kernel<int64_t>, dim3(1), dim3(BC_THREADS), lds, st, (const int64_t *)A, lda,
-                           m, n, make_mod(p), status);
+        PLUQ_LAUNCH(bc_rpm_kernel<int64_t>, dim3(1), dim3(BC_THREADS), 0, st, (const int64_t *)A, lda, m, n,
+                    make_mod(p), kchunk, status);
         break;
     case DT_F64:
-        hipLaunchKernelGGL(bc_rpm_kernel<double>, dim3(1), dim3(BC_THREADS), lds, st, (const double *)A, lda,
-                           m, n, make_mod(p), status);
+        PLUQ_LAUNCH(bc_rpm_kernel<double>, dim3(1), dim3(BC_THREADS), 0, st, (const double *)A, lda, m, n,
+                    make_mod(p), kchunk, status);
         break;
     case DT_I32:
-        hipLaunchKernelGGL(bc_rpm_kernel<int32_t>, dim3(1), dim3(BC_THREADS), lds, st, (const int32_t *)A, lda,
-                           m, n, make_mod(p), status);
+        PLUQ_LAUNCH(bc_rpm_kernel<int32_t>, dim3(1), dim3(BC_THREADS), 0, st, (const int32_t *)A, lda, m, n,
+                    make_mod(p), kchunk, status);
         break;
     default: return hipErrorInvalidValue;
     }

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
 
 template <typename T, int BM, int BN>
 static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
-    hipLaunchKernelGGL((modmm_f64_kernel<T, BM, BN>), dim3(total), dim3(256), 0, st, args);
+    PLUQ_LAUNCH((modmm_f64_kernel<T, BM, BN>), dim3(total), dim3(256), 0, st, args);
     return hipGetLastError();
 }
 

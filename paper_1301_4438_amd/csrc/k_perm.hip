@@ -67,15 +67,15 @@ hipError_t launch_gather2d(int dtype, const void *src, int64_t lds, void *dst, i
     const dim3 g = grid2d(rows, cols);
     switch (dtype) {
     case DT_I64:
-        hipLaunchKernelGGL(gather2d_kernel<int64_t>, g, dim3(PTHREADS), 0, st, (const int64_t *)src, lds,
+        PLUQ_LAUNCH(gather2d_kernel<int64_t>, g, dim3(PTHREADS), 0, st, (const int64_t *)src, lds,
                            (int64_t *)dst, ldd, rows, cols, rmap, cmap);
         break;
     case DT_F64:
-        hipLaunchKernelGGL(gather2d_kernel<double>, g, dim3(PTHREADS), 0, st, (const double *)src, lds,
+        PLUQ_LAUNCH(gather2d_kernel<double>, g, dim3(PTHREADS), 0, st, (const double *)src, lds,
                            (double *)dst, ldd, rows, cols, rmap, cmap);
         break;
     case DT_I32:
-        hipLaunchKernelGGL(gather2d_kernel<int32_t>, g, dim3(PTHREADS), 0, st, (const int32_t *)src, lds,
+        PLUQ_LAUNCH(gather2d_kernel<int32_t>, g, dim3(PTHREADS), 0, st, (const int32_t *)src, lds,
                            (int32_t *)dst, ldd, rows, cols, rmap, cmap);
         break;
     default: return hipErrorInvalidValue;
@@ -89,13 +89,13 @@ hipError_t launch_zscan(int dtype, const void *A, int64_t lda, int64_t rows, int
     const dim3 g = grid2d(rows, cols);
     switch (dtype) {
     case DT_I64:
-        hipLaunchKernelGGL(zscan_kernel<int64_t>, g, dim3(PTHREADS), 0, st, (const int64_t *)A, lda, rows, cols, flag, gen);
+        PLUQ_LAUNCH(zscan_kernel<int64_t>, g, dim3(PTHREADS), 0, st, (const int64_t *)A, lda, rows, cols, flag, gen);
         break;
     case DT_F64:
-        hipLaunchKernelGGL(zscan_kernel<double>, g, dim3(PTHREADS), 0, st, (const double *)A, lda, rows, cols, flag, gen);
+        PLUQ_LAUNCH(zscan_kernel<double>, g, dim3(PTHREADS), 0, st, (const double *)A, lda, rows, cols, flag, gen);
         break;
     case DT_I32:
-        hipLaunchKernelGGL(zscan_kernel<int32_t>, g, dim3(PTHREADS), 0, st, (const int32_t *)A, lda, rows, cols, flag, gen);
+        PLUQ_LAUNCH(zscan_kernel<int32_t>, g, dim3(PTHREADS), 0, st, (const int32_t *)A, lda, rows, cols, flag, gen);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -108,13 +108,13 @@ hipError_t launch_rangescan(int dtype, const void *A, int64_t lda, int64_t rows,
     const dim3 g = grid2d(rows, cols);
     switch (dtype) {
     case DT_I64:
-        hipLaunchKernelGGL(rangescan_kernel<int64_t>, g, dim3(PTHREADS), 0, st, (const int64_t *)A, lda, rows, cols, p, flag, gen);
+        PLUQ_LAUNCH(rangescan_kernel<int64_t>, g, dim3(PTHREADS), 0, st, (const int64_t *)A, lda, rows, cols, p, flag, gen);
         break;
     case DT_F64:
-        hipLaunchKernelGGL(rangescan_kernel<double>, g, dim3(PTHREADS), 0, st, (const double *)A, lda, rows, cols, p, flag, gen);
+        PLUQ_LAUNCH(rangescan_kernel<double>, g, dim3(PTHREADS), 0, st, (const double *)A, lda, rows, cols, p, flag, gen);
         break;
     case DT_I32:
-        hipLaunchKernelGGL(rangescan_kernel<int32_t>, g, dim3(PTHREADS), 0, st, (const int32_t *)A, lda, rows, cols, p, flag, gen);
+        PLUQ_LAUNCH(rangescan_kernel<int32_t>, g, dim3(PTHREADS), 0, st, (const int32_t *)A, lda, rows, cols, p, flag, gen);
         break;
     default: return hipErrorInvalidValue;
     }

@@ -41,6 +41,13 @@ hipError_t launch_trsm_run_leaf(int dtype, void *B, int64_t ldb, int64_t nrows,
                                 const void *U, int64_t ldu, int nb, double p, int kchunk,
                                 hipStream_t st);
 
+// Inverses of the 64 x 64 diagonal blocks of an r x r triangle (side 0:
+// unit lower, side 1: upper non-unit), written as I - T_qq^{-1} (canonical,
+// row-major, leading dimension 64) at W + q * 64 * 64.
+constexpr int TRSM_NB = 64;
+hipError_t launch_trsm_diag_inv(int dtype, int side, const void *T, int64_t ldt, int64_t r, void *W,
+                                double p, int kchunk, hipStream_t st);
+
 // dst[i][j] = src[rmap ? rmap[i] : i][cmap ? cmap[j] : j], rows x cols.
 hipError_t launch_gather2d(int dtype, const void *src, int64_t lds, void *dst, int64_t ldd,
                            int64_t rows, int64_t cols, const int32_t *rmap,
@@ -55,23 +62,46 @@ hipError_t launch_rangescan(int dtype, const void *A, int64_t lda, int64_t rows,
                             int64_t cols, double p, int32_t *flag, int32_t gen,
                             hipStream_t st);
 
-// Write the int64 vector v (length n) to dst.
-hipError_t launch_store_i64(int64_t *dst, const int32_t *src, int64_t n, hipStream_t st);
-
-// Base case, elimination without pivoting of the m x n tile (m*n <= cap),
+// Base case, elimination without pivoting of the m x n tile (m, n <= 128),
 // gathered through rmap/cmap when given.  r_known < 0: optimistic mode (stop
 // on the first zero pivot; success iff the trailing block is zero there);
 // otherwise exactly r_known pivots are taken.  status[0] = r, status[1] = 1
 // on success (tile written back in packed order), 0 on failure (tile left
 // untouched).
 hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
-                        const int32_t *cmap, int r_known, double p, int32_t *status,
-                        hipStream_t st);
+                        const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *inv_table,
+                        int32_t *status, hipStream_t st);
+// Table of inverses mod p (p <= 65536) used by bc_lu from LDS: bytes of the
+// device buffer (0 when the device cannot hold it in LDS or p is larger),
+// and the kernel that fills it.
+size_t bc_table_bytes(double p);
+// Largest tile dimension bc_lu accepts for this modulus when the table is used.
+int bc_tile_limit(double p);
+constexpr size_t BC_TABLE_RESERVE = 65536 * sizeof(uint16_t);
+hipError_t launch_build_inv_table(uint16_t *tab, double p, hipStream_t st);
 // Base case, rank profile matrix of the m x n tile: status[0] = r and
 // status[1 + i] = pivot column of row i or -1.  The tile is not modified.
-hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p,
+hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,
                          int32_t *status, hipStream_t st);
-int bc_capacity();        // maximum m*n of a base-case tile
-hipError_t bc_init();     // raise the dynamic LDS limit of the base-case kernels
+int bc_capacity();        // maximum rows (and columns) of a base-case tile
+hipError_t bc_init();     // one-time set-up of the base-case kernels
 
 }  // namespace pluq
+
+#include <hip/hip_ext.h>
+
+namespace pluq {
+
+// Events attached to the next kernel dispatch when kernels are being timed
+// (null otherwise).  The events are recorded by the dispatch itself, so they
+// bracket the kernel's execution and nothing else.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+}  // namespace pluq
+
+#define PLUQ_LAUNCH(kernel, grid, block, shm, st, ...)                                              \
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, st, ::pluq::g_launch_events.start,            \
+                          ::pluq::g_launch_events.stop, 0, __VA_ARGS__)
