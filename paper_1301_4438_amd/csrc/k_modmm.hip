@@ -8,14 +8,18 @@
 // product is at most (p/2)^2 and a sum of `kchunk` of them plus a reduced
 // residue stays below 2^52: every partial sum is an exactly representable
 // integer whatever the summation order inside the matrix core.  The
-// accumulator is reduced once per kchunk terms (delayed reduction, Section 6)
-// and once in the epilogue, where C is read, updated and written back.
+// accumulator starts from C (loaded when the kernel starts, so no dependent
+// read is left for the end), A is negated on load, the accumulator is reduced
+// once per kchunk terms (delayed reduction, Section 6) and once before the
+// store.
 //
 // Tiling: 256 threads = 4 waves in a 2 x 2 grid; each wave owns a
 // (BM/2) x (BN/2) sub-tile made of 16 x 16 blocks computed with
-// v_mfma_f64_16x16x4_f64.  A and B panels of depth 16 are staged in LDS with
-// k as the slow index, so the 16 lanes sharing a k read consecutive words.
-// The next panel is fetched into registers while the current one is used.
+// v_mfma_f64_16x16x4_f64.  Panels of depth BK are staged in LDS (A row-major,
+// B row-major, both padded); global loads are lane-contiguous row segments;
+// the next panel is fetched into registers while the current one is used.
+// A 64 x 64 tile uses BK = 64, so an update with K <= 64 (the leaves of the
+// triangular solves and the deep Schur updates) needs a single load phase.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -30,18 +34,15 @@ struct MMArgs {
     ModP mod;
 };
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
-    constexpr int BK = 16;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
-    constexpr int PAD = 2;
-    constexpr int ELA = BM * BK / 256;   // A elements loaded per thread
-    constexpr int ELB = BN * BK / 256;   // B elements loaded per thread
-    constexpr int TPRA = BK / ELA;       // threads per A row
-    constexpr int TPRB = BN / ELB;       // threads per B row
-    __shared__ double As[BK][BM + PAD];
-    __shared__ double Bs[BK][BN + PAD];
+    constexpr int ELA = BM * BK / 256;   // A elements loaded per thread and panel
+    constexpr int ELB = BN * BK / 256;   // B elements loaded per thread and panel
+    constexpr int PA = BK + 1, PB = BN + 1;
+    __shared__ double As[BM * PA];
+    __shared__ double Bs[BK * PB];
 
     const int tile = blockIdx.x;
     int pi = 0;
@@ -61,20 +62,31 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
     const int wm0 = (wave >> 1) * WM;
     const int wn0 = (wave & 1) * WN;
 
-    const int ar = tid / TPRA, ak = (tid % TPRA) * ELA;
-    const int bk = tid / TPRB, bc = (tid % TPRB) * ELB;
+    // accumulator <- C (canonical).  v_mfma_f64_16x16x4_f64 keeps, for its
+    // 16 x 16 block, rows lane/16 + 4v and column lane%16 in lane `lane`.
+    T *C = (T *)P.C;
+    v4d acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = row0 + wm0 + i * 16 + (lane >> 4) + 4 * v;
+                const int gc = col0 + wn0 + j * 16 + (lane & 15);
+                acc[i][j][v] = to_f64(C[(int64_t)min(gr, M - 1) * P.ldc + min(gc, N - 1)]);
+            }
 
     const int K0 = P.K[0], K1 = P.K[1];
     const int steps0 = (K0 + BK - 1) / BK;
     const int steps = steps0 + (K1 + BK - 1) / BK;
 
-    v4d acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
-
-    double ra[ELA], rb[ELB];
+    // Panel loads are branch-free: addresses are clamped into the operand (so
+    // every load is valid) and out-of-range entries are masked to zero when
+    // the raw values are converted, at the LDS store of the next iteration.
+    // The loads of panel s+1 are thus all in flight during panel s's MFMAs.
+    T ra[ELA], rb[ELB];
+    uint32_t ma = 0, mb = 0;   // validity bit per loaded element
     auto load_step = [&](int s) {
         const int pair = (s < steps0) ? 0 : 1;
         const int k0 = (pair == 0 ? s : s - steps0) * BK;
@@ -82,21 +94,21 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
         const T *A = (const T *)P.A[pair];
         const T *B = (const T *)P.B[pair];
         const int64_t lda = P.lda[pair], ldb = P.ldb[pair];
-        const int grow = row0 + ar;
+        ma = 0;
+        mb = 0;
 #pragma unroll
         for (int e = 0; e < ELA; ++e) {
-            const int kk = k0 + ak + e;
-            double v = 0.0;
-            if (grow < M && kk < K) v = to_sym(to_f64(A[(int64_t)grow * lda + kk]), mod);
-            ra[e] = v;
+            const int idx = tid + 256 * e;
+            const int gr = row0 + idx / BK, gk = k0 + idx % BK;
+            ma |= (uint32_t)(gr < M && gk < K) << e;
+            ra[e] = A[(int64_t)min(gr, M - 1) * lda + min(gk, K - 1)];
         }
-        const int kb = k0 + bk;
 #pragma unroll
         for (int e = 0; e < ELB; ++e) {
-            const int gc = col0 + bc + e;
-            double v = 0.0;
-            if (kb < K && gc < N) v = to_sym(to_f64(B[(int64_t)kb * ldb + gc]), mod);
-            rb[e] = v;
+            const int idx = tid + 256 * e;
+            const int gk = k0 + idx / BN, gc = col0 + idx % BN;
+            mb |= (uint32_t)(gk < K && gc < N) << e;
+            rb[e] = B[(int64_t)min(gk, K - 1) * ldb + min(gc, N - 1)];
         }
     };
 
@@ -105,9 +117,17 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
     for (int s = 0; s < steps; ++s) {
         __syncthreads();
 #pragma unroll
-        for (int e = 0; e < ELA; ++e) As[ak + e][ar] = ra[e];
+        for (int e = 0; e < ELA; ++e) {
+            const int idx = tid + 256 * e;
+            const double v = -to_sym(to_f64(ra[e]), mod);
+            As[(idx / BK) * PA + idx % BK] = ((ma >> e) & 1u) ? v : 0.0;
+        }
 #pragma unroll
-        for (int e = 0; e < ELB; ++e) Bs[bk][bc + e] = rb[e];
+        for (int e = 0; e < ELB; ++e) {
+            const int idx = tid + 256 * e;
+            const double v = to_sym(to_f64(rb[e]), mod);
+            Bs[(idx / BN) * PB + idx % BN] = ((mb >> e) & 1u) ? v : 0.0;
+        }
         __syncthreads();
         if (s + 1 < steps) load_step(s + 1);
         if (kacc + BK > args.kchunk) {
@@ -124,9 +144,9 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
             const int kr = ks * 4 + (lane >> 4);
             double a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = As[kr][wm0 + i * 16 + (lane & 15)];
+            for (int i = 0; i < FM; ++i) a[i] = As[(wm0 + i * 16 + (lane & 15)) * PA + kr];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = Bs[kr][wn0 + j * 16 + (lane & 15)];
+            for (int j = 0; j < FN; ++j) b[j] = Bs[kr * PB + wn0 + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -136,9 +156,6 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
         kacc += BK;
     }
 
-    // Epilogue: C <- (C - acc) mod p.  For v_mfma_f64_16x16x4_f64 the lane
-    // holds rows lane/16 + 4v of its block, column lane%16.
-    T *C = (T *)P.C;
     bool nz = false;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -149,19 +166,23 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
                 const int gr = row0 + wm0 + i * 16 + (lane >> 4) + 4 * v;
                 const int gc = col0 + wn0 + j * 16 + (lane & 15);
                 if (gr < M && gc < N) {
-                    T *cp = C + (int64_t)gr * P.ldc + gc;
-                    const double x = mod_reduce(to_f64(*cp) - acc[i][j][v], mod);
-                    *cp = from_f64<T>(x);
+                    const double x = mod_reduce(acc[i][j][v], mod);
+                    C[(int64_t)gr * P.ldc + gc] = from_f64<T>(x);
                     nz |= (x != 0.0);
                 }
             }
     if (nz && P.nzflag) *P.nzflag = P.nzgen;
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int BK>
 static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
-    PLUQ_LAUNCH((modmm_f64_kernel<T, BM, BN>), dim3(total), dim3(256), 0, st, args);
+    PLUQ_LAUNCH((modmm_f64_kernel<T, BM, BN, BK>), dim3(total), dim3(256), 0, st, args);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_dt(MMArgs &args, int big, int total, hipStream_t st) {
+    return big == 128 ? launch_t<T, 128, 128, 32>(args, total, st) : launch_t<T, 64, 64, 64>(args, total, st);
 }
 
 hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
@@ -184,8 +205,8 @@ hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, in
         pb.tileStart = total;
         pb.tilesN = (int)cdiv64(pb.N, big);
         total += (int)(cdiv64(pb.M, big) * pb.tilesN);
-        if (pb.K[0] <= 0) { pb.K[0] = 0; }
-        if (pb.K[1] <= 0) { pb.K[1] = 0; }
+        if (pb.K[0] <= 0) pb.K[0] = 0;
+        if (pb.K[1] <= 0) pb.K[1] = 0;
     }
     args.count = n;
     args.kchunk = kchunk;
@@ -193,12 +214,9 @@ hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, in
     args.mod.pinv = 1.0 / p;
     args.mod.half = (double)((int64_t)p / 2);
     switch (dtype) {
-    case DT_I64:
-        return big == 128 ? launch_t<int64_t, 128, 128>(args, total, st) : launch_t<int64_t, 64, 64>(args, total, st);
-    case DT_F64:
-        return big == 128 ? launch_t<double, 128, 128>(args, total, st) : launch_t<double, 64, 64>(args, total, st);
-    case DT_I32:
-        return big == 128 ? launch_t<int32_t, 128, 128>(args, total, st) : launch_t<int32_t, 64, 64>(args, total, st);
+    case DT_I64: return launch_dt<int64_t>(args, big, total, st);
+    case DT_F64: return launch_dt<double>(args, big, total, st);
+    case DT_I32: return launch_dt<int32_t>(args, big, total, st);
     }
     return hipErrorInvalidValue;
 }
