@@ -27,8 +27,10 @@
  *    recursive calls with floor(m/2) x floor(n/2) splits, the non-pivot rows
  *    and columns after them in ascending order, and [L\U V; M 0] the LU
  *    factorisation without pivoting of A_in[P, Q].  No option changes it.
- *  - Supported moduli: p prime, 2 <= p < 2^26 (every product of two reduced
- *    residues is then exact in an IEEE double).  Primality is not checked.
+ *  - Moduli: p prime, 2 <= p < 2^26 is accepted (every product of two reduced
+ *    residues is then exact in an IEEE double); the forms narrow it further
+ *    (PLUQ_ERR_UNSUPPORTED): FP64 needs p < 2^25, INT8 p <= 65536, FP32
+ *    p < 2^11.  Primality is not checked.
  *  - Device pointers are HIP device allocations of the calling process; host
  *    pointers are ordinary host memory.  The caller owns every buffer.
  *  - `stream` is a hipStream_t (NULL = the default stream).  All device work
@@ -70,12 +72,19 @@ typedef enum { PLUQ_I64 = 0, PLUQ_F64 = 1, PLUQ_I32 = 2 } pluq_dtype;
  *   FP64 -- float64 matrix cores, residues in symmetric form, products
  *           accumulated exactly and reduced once per chunk of the inner
  *           dimension (delayed reduction, Section 6): needs a chunk K >= 16
- *           with K * ((p-1)/2)^2 + 4p < 2^52, i.e. p < 2^26.
- *   INT8 -- residues split into signed 8-bit limbs on int8 matrix cores with
- *           int32 accumulation, recombined exactly in float64 (p <= 65521,
- *           one limb for p <= 251).
- *   FP32 -- float32 matrix cores on symmetric residues for p < 2^11, with the
- *           inner dimension chunked so every partial sum is below 2^24.
+ *           with K * ((p-1)/2)^2 + 4p < 2^52, i.e. p < 2^25.
+ *   INT8 -- each residue, moved into the window [-32896, 32639] (a or a - p),
+ *           is written as two signed base-256 digits (one digit in
+ *           [-128, 127] when p <= 256); the limb products run on the int8
+ *           matrix cores with int32 accumulation and are recombined exactly
+ *           in float64 (p <= 65536).  Updates smaller than about 2^26
+ *           multiply-adds stay in the FP64 kernel.  Needs the larger
+ *           workspace that pluq_workspace_size reports for this form.
+ *   FP32 -- float32 matrix cores on symmetric residues, reduced (in float64)
+ *           after at most K products with K * (p/2)^2 + p < 2^24, K >= 16,
+ *           i.e. p < 2^11 (K = 1072 for p = 251).
+ * The triangular-solve inverses and the base case use float64 arithmetic in
+ * every form.  A form that cannot be exact for p gives PLUQ_ERR_UNSUPPORTED.
  */
 typedef enum { PLUQ_FORM_FP64 = 0, PLUQ_FORM_INT8 = 1, PLUQ_FORM_FP32 = 2 } pluq_form;
 
@@ -165,8 +174,9 @@ pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n,
  * (lda), B k x n (ldb), all device, row-major, element type dt, canonical
  * residues.  `form` selects the matrix-core arithmetic (pluq_form); results
  * are identical for every form.  dWork/work_bytes: scratch for the INT8
- * form's limb planes (>= pluq_modmm_workspace_size; may be NULL otherwise).
- * Asynchronous on `stream`.
+ * form's limb planes (>= pluq_modmm_workspace_size, 256-byte aligned; may be
+ * NULL when that is 0).  In the INT8 form this entry point always uses the
+ * int8 matrix cores, whatever the size.  Asynchronous on `stream`.
  */
 size_t pluq_modmm_workspace_size(int64_t m, int64_t n, int64_t k, int32_t form);
 pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
@@ -217,7 +227,8 @@ enum {
     PLUQ_K_PERM = 2,      /* row / column permutations */
     PLUQ_K_BASECASE = 3,  /* base-case tiles */
     PLUQ_K_SCAN = 4,      /* zero / range scans */
-    PLUQ_K_COUNT = 5
+    PLUQ_K_LIMB = 5,      /* INT8 form: digit-plane split of MM operands */
+    PLUQ_K_COUNT = 6
 };
 typedef struct {
     int64_t launches;

@@ -46,7 +46,7 @@ class pluq_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
-KERNEL_CLASSES = ["modmm", "trsm_leaf", "perm", "basecase", "scan"]
+KERNEL_CLASSES = ["modmm", "trsm_leaf", "perm", "basecase", "scan", "limb"]
 
 
 def load():

@@ -40,6 +40,26 @@ int64_t fp64_kchunk(uint64_t p) {
     return kc;
 }
 
+// FP32 form: largest multiple of 16 such that kchunk * (p/2)^2 + p < 2^24
+// (0 when below 16: the form cannot be exact for this modulus).
+int64_t fp32_kchunk(uint64_t p) {
+    const double half = (double)(p / 2);
+    const double lim = 16777216.0 - (double)p;
+    double k = half > 0 ? lim / (half * half) : 1e9;
+    if (k > (double)(1 << 30)) k = (double)(1 << 30);
+    int64_t kc = (int64_t)k;
+    kc -= kc % 16;
+    return kc >= 16 ? kc : 0;
+}
+
+// Bytes of digit planes for the INT8-limb form of an m x n decomposition:
+// enough for one KMAX_I8-deep piece of any update (rows + columns <= m + n).
+size_t limb_bytes_for(int64_t m, int64_t n, uint64_t p) {
+    const int nl = i8_limbs((double)p);
+    const int64_t kmax = std::min<int64_t>((std::min(m, n) + 63) / 64 * 64 + 128, KMAX_I8);
+    return (size_t)nl * (size_t)(m + n) * (size_t)kmax;
+}
+
 struct Pinned {
     int32_t *idx = nullptr;
     size_t idx_cap = 0;
@@ -86,8 +106,8 @@ int bc_cap() {
 }
 
 struct Layout {
-    size_t stat_off, idx_off, tab_off, w_off, scratch_off, total;
-    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes;
+    size_t stat_off, idx_off, tab_off, w_off, scratch_off, limb_off, total;
+    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes, limb_bytes;
 };
 
 // Diagonal-block inverses of a triangle of order r (TRSM).
@@ -95,7 +115,7 @@ size_t trsm_w_bytes(int64_t r, size_t esz) {
     return (size_t)((r + TRSM_NB - 1) / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
 }
 
-Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p) {
+Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form) {
     Layout L;
     L.idx_elems = (size_t)(4 * (m + n) + 65536);
     const size_t full = (size_t)m * (size_t)n * esz;
@@ -109,7 +129,9 @@ Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p) {
     L.w_bytes = trsm_w_bytes(std::min(m, n), esz);
     L.w_off = L.tab_off + align_up(L.tab_bytes);
     L.scratch_off = L.w_off + align_up(L.w_bytes);
-    L.total = L.scratch_off + align_up(L.scratch_bytes);
+    L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0) ? limb_bytes_for(m, n, p) : 0;
+    L.limb_off = L.scratch_off + align_up(L.scratch_bytes);
+    L.total = L.limb_off + align_up(L.limb_bytes);
     return L;
 }
 
@@ -125,9 +147,14 @@ pluq_status check_common(int64_t m, int64_t n, int64_t lda, pluq_dtype dt, uint6
     return PLUQ_OK;
 }
 
+// Every form keeps the FP64 kernels for the triangular-solve inverses and the
+// base case, so all of them need the FP64 bound as well.
 pluq_status form_check(int form, uint64_t p) {
-    if (form == PLUQ_FORM_FP64) return fp64_kchunk(p) >= 16 ? PLUQ_OK : PLUQ_ERR_UNSUPPORTED;
-    return PLUQ_ERR_UNSUPPORTED;  // other forms: not available in this build
+    if (fp64_kchunk(p) < 16) return PLUQ_ERR_UNSUPPORTED;
+    if (form == PLUQ_FORM_FP64) return PLUQ_OK;
+    if (form == PLUQ_FORM_INT8) return i8_limbs((double)p) > 0 ? PLUQ_OK : PLUQ_ERR_UNSUPPORTED;
+    if (form == PLUQ_FORM_FP32) return fp32_kchunk(p) >= 16 ? PLUQ_OK : PLUQ_ERR_UNSUPPORTED;
+    return PLUQ_ERR_ARG;
 }
 
 }  // namespace
@@ -152,7 +179,7 @@ const char *pluq_version(void) { return "pluq-mi355x 0.1 (gfx950)"; }
 
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
-    return layout(m, n, esize(dt), p).total;
+    return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64).total;
 }
 
 pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
@@ -166,7 +193,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
     const int form = opts ? opts->form : PLUQ_FORM_FP64;
     if ((s = form_check(form, p)) != PLUQ_OK) return s;
     const size_t esz = esize(dt);
-    const Layout L = layout(m, n, esz, p);
+    const Layout L = layout(m, n, esz, p, form);
     if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
     if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
 
@@ -179,6 +206,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.p = p;
         c.form = form;
         c.kchunk = (int)std::min<int64_t>(fp64_kchunk(p), 1 << 30);
+        c.kchunk32 = (int)fp32_kchunk(p);
         c.leaf_nb = (opts && opts->trsm_leaf_override > 0) ? opts->trsm_leaf_override : 64;
         c.cap = bc_cap();
         if (c.cap <= 0) return PLUQ_ERR_DEVICE;
@@ -193,6 +221,10 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.scratch = w + L.scratch_off;
         c.scratch_bytes = L.scratch_bytes;
         c.trsm_w = w + L.w_off;
+        if (L.limb_bytes) {
+            c.limb = w + L.limb_off;
+            c.limb_bytes = L.limb_bytes;
+        }
         c.h_idx = g_pin.idx;
         c.h_stat = g_pin.stat;
         if (L.tab_bytes && bc_table_bytes((double)p) && m > 0 && n > 0) {
@@ -290,14 +322,15 @@ pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n,
 }
 
 size_t pluq_modmm_workspace_size(int64_t m, int64_t n, int64_t k, int32_t form) {
-    (void)m; (void)n; (void)k; (void)form;
-    return 0;
+    if (m < 0 || n < 0 || k < 0) return 0;
+    if (form != PLUQ_FORM_INT8 || m == 0 || n == 0 || k == 0) return 0;
+    // two digit planes of one KMAX_I8-deep piece of A and B
+    return align_up((size_t)2 * (size_t)(m + n) * (size_t)std::min<int64_t>((k + 63) / 64 * 64, KMAX_I8));
 }
 
 pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
                        const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form, void *dWork,
                        size_t work_bytes, void *stream) {
-    (void)dWork; (void)work_bytes;
     if (m < 0 || n < 0 || k < 0 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return PLUQ_ERR_ARG;
     if (esize(dt) == 0) return PLUQ_ERR_ARG;
     if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
@@ -307,6 +340,9 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, c
     if (!dC || (k > 0 && (!dA || !dB))) return PLUQ_ERR_ARG;
     if (ldc < n || (k > 0 && (lda < k || ldb < n))) return PLUQ_ERR_ARG;
     if (k == 0) return PLUQ_OK;
+    const size_t need = pluq_modmm_workspace_size(m, n, k, form);
+    if (need && (!dWork || work_bytes < need)) return PLUQ_ERR_WORKSPACE;
+    if (need && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
     MMProblem pb;
     std::memset(&pb, 0, sizeof(pb));
     pb.C = dC;
@@ -318,8 +354,27 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, c
     pb.B[0] = dB;
     pb.ldb[0] = ldb;
     pb.K[0] = (int32_t)k;
-    hipError_t e = launch_modmm_f64((int)dt, &pb, 1, (double)p, (int)fp64_kchunk(p), (hipStream_t)stream);
-    return e == hipSuccess ? PLUQ_OK : PLUQ_ERR_DEVICE;
+    try {
+        Ctx c;
+        c.dt = (int)dt;
+        c.esz = esize(dt);
+        c.p = p;
+        c.form = form;
+        c.kchunk = (int)fp64_kchunk(p);
+        c.kchunk32 = (int)fp32_kchunk(p);
+        c.st = (hipStream_t)stream;
+        if (form == PLUQ_FORM_INT8) {
+            // the kernel-level entry always takes the int8 path
+            c.limb = (char *)dWork;
+            c.limb_bytes = work_bytes;
+            if (!c.mm_i8(pb)) return PLUQ_ERR_WORKSPACE;
+        } else {
+            c.mm(&pb, 1);
+        }
+    } catch (const DeviceError &) {
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
 }
 
 size_t pluq_trsm_workspace_size(int64_t r, pluq_dtype dt) {
@@ -347,6 +402,7 @@ pluq_status pluq_trsm(int32_t side, int64_t r, int64_t other, const void *dT, in
         c.p = p;
         c.form = form;
         c.kchunk = (int)fp64_kchunk(p);
+        c.kchunk32 = (int)fp32_kchunk(p);
         c.st = (hipStream_t)stream;
         c.trsm_w = (char *)dWork;
         if (side == 0)

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "driver.hpp"
+#include "pluq.h"
 
 namespace pluq {
 
@@ -169,6 +170,19 @@ void Ctx::mm(MMProblem *probs, int n) {
     for (int q = 0; q < n; ++q)
         if (probs[q].M > 0 && probs[q].N > 0 && (probs[q].K[0] > 0 || probs[q].K[1] > 0)) probs[live++] = probs[q];
     if (!live) return;
+    if (form == PLUQ_FORM_INT8 && limb) {
+        // Large updates go to the int8 matrix cores; small ones (latency
+        // bound either way) stay in the FP64 kernel, grouped.
+        int rest = 0;
+        for (int q = 0; q < live; ++q) {
+            const MMProblem &pb = probs[q];
+            const int64_t K = (int64_t)std::max(pb.K[0], 0) + std::max(pb.K[1], 0);
+            const bool big = pb.M >= 128 && pb.N >= 128 && K >= 128 && (double)pb.M * pb.N * K >= I8_MIN_WORK;
+            if (!(big && mm_i8(pb))) probs[rest++] = pb;
+        }
+        live = rest;
+        if (!live) return;
+    }
     double flops = 0, bytes = 0;
     for (int q = 0; q < live; ++q) {
         const double M = probs[q].M, N = probs[q].N;
@@ -179,7 +193,84 @@ void Ctx::mm(MMProblem *probs, int n) {
             bytes += M * K + K * N;
         }
     }
-    launch(K_MODMM, flops, bytes * (double)esz, [&] { return launch_modmm_f64(dt, probs, live, (double)p, kchunk, st); });
+    if (form == PLUQ_FORM_FP32)
+        launch(K_MODMM, flops, bytes * (double)esz, [&] { return launch_modmm_f32(dt, probs, live, (double)p, kchunk32, st); });
+    else
+        launch(K_MODMM, flops, bytes * (double)esz, [&] { return launch_modmm_f64(dt, probs, live, (double)p, kchunk, st); });
+}
+
+// One update in the INT8-limb form: the inner dimension (both operand pairs)
+// is cut into pieces of at most KMAX_I8 positions (and what the digit-plane
+// workspace holds); each piece is split into digit planes and multiplied,
+// updating C in place.  Only the last piece reports non-zero outputs.
+// Returns false (nothing launched) when the workspace cannot hold one
+// 64-deep piece.
+bool Ctx::mm_i8(const MMProblem &pb) {
+    const int nl = i8_limbs((double)p);
+    const int64_t M = pb.M, N = pb.N;
+    int64_t ks = (int64_t)(limb_bytes / ((size_t)nl * (size_t)(M + N))) / 64 * 64;
+    ks = std::min<int64_t>(ks, KMAX_I8);
+    if (nl == 0 || ks < 64) return false;
+    struct Seg { int pair; int64_t k0, len; };
+    std::vector<Seg> segs;
+    for (int s = 0; s < 2; ++s)
+        for (int64_t k0 = 0; k0 < pb.K[s]; k0 += ks) segs.push_back({s, k0, std::min<int64_t>(ks, pb.K[s] - k0)});
+    int8_t *a0 = (int8_t *)limb;
+    size_t i = 0;
+    while (i < segs.size()) {
+        // pack consecutive pieces while their padded widths fit in ks
+        size_t j = i;
+        int64_t kp = 0;
+        while (j < segs.size() && j - i < 2 && kp + (segs[j].len + 63) / 64 * 64 <= ks) {
+            kp += (segs[j].len + 63) / 64 * 64;
+            ++j;
+        }
+        int8_t *a1 = a0 + M * kp, *b0 = a0 + (size_t)nl * M * kp, *b1 = b0 + N * kp;
+        SplitJob jobs[SPLIT_MAX_JOBS];
+        int nj = 0;
+        int64_t koff = 0;
+        for (size_t q = i; q < j; ++q) {
+            const Seg &sg = segs[q];
+            const int64_t w = (sg.len + 63) / 64 * 64;
+            SplitJob ja;
+            ja.src = (const char *)pb.A[sg.pair] + sg.k0 * (int64_t)esz;
+            ja.ld = pb.lda[sg.pair];
+            ja.rows = (int32_t)M;
+            ja.K = (int32_t)sg.len;
+            ja.Kp = (int32_t)w;
+            ja.trans = 0;
+            ja.dst0 = a0 + koff;
+            ja.dst1 = a1 + koff;
+            ja.ldd = kp;
+            jobs[nj++] = ja;
+            SplitJob jb;
+            jb.src = (const char *)pb.B[sg.pair] + sg.k0 * pb.ldb[sg.pair] * (int64_t)esz;
+            jb.ld = pb.ldb[sg.pair];
+            jb.rows = (int32_t)N;
+            jb.K = (int32_t)sg.len;
+            jb.Kp = (int32_t)w;
+            jb.trans = 1;
+            jb.dst0 = b0 + koff;
+            jb.dst1 = b1 + koff;
+            jb.ldd = kp;
+            jobs[nj++] = jb;
+            koff += w;
+        }
+        const double split_bytes = (double)(M + N) * (double)kp * ((double)esz + nl);
+        launch(K_LIMB, 0, split_bytes, [&] { return launch_limb_split(dt, jobs, nj, (double)p, st); });
+        int64_t klen = 0;
+        for (size_t q = i; q < j; ++q) klen += segs[q].len;
+        const bool last = (j == segs.size());
+        const int8_t *pa[2] = {a0, a1}, *pbp[2] = {b0, b1};
+        const double flops = 2.0 * (double)M * (double)N * (double)klen;
+        const double bytes = 2.0 * M * N * (double)esz + (double)(M + N) * (double)kp * nl;
+        launch(K_MODMM, flops, bytes, [&] {
+            return launch_modmm_i8(dt, pb.C, pb.ldc, (int)M, (int)N, (int)kp, pa, pbp, kp, kp, (double)p,
+                                   last ? pb.nzflag : nullptr, pb.nzgen, st);
+        });
+        i = j;
+    }
+    return true;
 }
 
 static MMProblem mmprob(void *C, int64_t ldc, int64_t M, int64_t N) {

@@ -19,8 +19,8 @@ struct Stats {
 extern thread_local Stats g_last_stats;
 
 // Per-kernel-class device timing (HIP events), per host thread.
-constexpr int KCLASSES = 5;
-enum KClass { K_MODMM = 0, K_TRSM = 1, K_PERM = 2, K_BASE = 3, K_SCAN = 4 };
+constexpr int KCLASSES = 6;
+enum KClass { K_MODMM = 0, K_TRSM = 1, K_PERM = 2, K_BASE = 3, K_SCAN = 4, K_LIMB = 5 };
 struct KStat {
     int64_t launches = 0;
     double ms = 0, flops = 0, bytes = 0;
@@ -42,6 +42,10 @@ struct Profiler {
     void discard();
 };
 extern thread_local Profiler g_prof;
+
+// INT8-limb form: updates with fewer multiply-adds than this stay in the FP64
+// kernel (a split launch costs more than it saves on small updates).
+constexpr double I8_MIN_WORK = 64.0 * 1024 * 1024;
 
 enum Zero { Z_UNKNOWN = 0, Z_ZERO = 1, Z_NONZERO = 2 };
 
@@ -74,6 +78,9 @@ struct Ctx {
     int32_t *d_stat = nullptr;
     uint16_t *inv_table = nullptr;   // inverses mod p for the base case (or null)
     char *trsm_w = nullptr;          // I - T_qq^{-1} blocks of the current solve
+    char *limb = nullptr;            // digit planes of the INT8-limb form (or null)
+    size_t limb_bytes = 0;
+    int kchunk32 = 0;                // FP32 form: products between reductions
     // pinned host mirrors
     int32_t *h_idx = nullptr;
     int32_t *h_stat = nullptr;
@@ -99,6 +106,7 @@ struct Ctx {
     void perm_rows(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
     void perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
     void mm(MMProblem *probs, int n);
+    bool mm_i8(const MMProblem &pb);
     void trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols);
     void trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r);
     void trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols);

@@ -20,12 +20,38 @@
 // the next panel is fetched into registers while the current one is used.
 // A 64 x 64 tile uses BK = 64, so an update with K <= 64 (the leaves of the
 // triangular solves and the deep Schur updates) needs a single load phase.
+//
+// The same kernel in float32 (CT = float, v_mfma_f32_16x16x4_f32) is the
+// FP32 form for small moduli: a float32 sum of integers is exact while it
+// stays below 2^24, so with |a| <= p/2 at most kchunk32 = (2^24 - p) / (p/2)^2
+// products (1072 for p = 251) are accumulated between reductions, which are
+// done in float64.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace pluq {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Accumulator vector and output-row layout of the matrix-core instruction
+// used for compute type CT.  Lane `lane` holds, in element v of its 16 x 16
+// block, row row(lane, v) and column lane % 16.
+template <typename CT> struct MfmaTraits;
+template <> struct MfmaTraits<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+    static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MfmaTraits<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+    static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
 
 struct MMArgs {
     MMProblem prob[MM_MAX_PROBLEMS];
@@ -34,15 +60,16 @@ struct MMArgs {
     ModP mod;
 };
 
-template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
+template <typename T, typename CT, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
+    typedef MfmaTraits<CT> MT;
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int ELA = BM * BK / 256;   // A elements loaded per thread and panel
     constexpr int ELB = BN * BK / 256;   // B elements loaded per thread and panel
     constexpr int PA = BK + 1, PB = BN + 1;
-    __shared__ double As[BM * PA];
-    __shared__ double Bs[BK * PB];
+    __shared__ CT As[BM * PA];
+    __shared__ CT Bs[BK * PB];
 
     const int tile = blockIdx.x;
     int pi = 0;
@@ -62,19 +89,18 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
     const int wm0 = (wave >> 1) * WM;
     const int wn0 = (wave & 1) * WN;
 
-    // accumulator <- C (canonical).  v_mfma_f64_16x16x4_f64 keeps, for its
-    // 16 x 16 block, rows lane/16 + 4v and column lane%16 in lane `lane`.
+    // accumulator <- C (canonical).
     T *C = (T *)P.C;
-    v4d acc[FM][FN];
+    typename MT::acc_t acc[FM][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gr = row0 + wm0 + i * 16 + (lane >> 4) + 4 * v;
+                const int gr = row0 + wm0 + i * 16 + MT::row(lane, v);
                 const int gc = col0 + wn0 + j * 16 + (lane & 15);
-                acc[i][j][v] = to_f64(C[(int64_t)min(gr, M - 1) * P.ldc + min(gc, N - 1)]);
+                acc[i][j][v] = (CT)to_f64(C[(int64_t)min(gr, M - 1) * P.ldc + min(gc, N - 1)]);
             }
 
     const int K0 = P.K[0], K1 = P.K[1];
@@ -119,14 +145,14 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
 #pragma unroll
         for (int e = 0; e < ELA; ++e) {
             const int idx = tid + 256 * e;
-            const double v = -to_sym(to_f64(ra[e]), mod);
-            As[(idx / BK) * PA + idx % BK] = ((ma >> e) & 1u) ? v : 0.0;
+            const CT v = (CT)-to_sym(to_f64(ra[e]), mod);
+            As[(idx / BK) * PA + idx % BK] = ((ma >> e) & 1u) ? v : (CT)0;
         }
 #pragma unroll
         for (int e = 0; e < ELB; ++e) {
             const int idx = tid + 256 * e;
-            const double v = to_sym(to_f64(rb[e]), mod);
-            Bs[(idx / BN) * PB + idx % BN] = ((mb >> e) & 1u) ? v : 0.0;
+            const CT v = (CT)to_sym(to_f64(rb[e]), mod);
+            Bs[(idx / BN) * PB + idx % BN] = ((mb >> e) & 1u) ? v : (CT)0;
         }
         __syncthreads();
         if (s + 1 < steps) load_step(s + 1);
@@ -136,13 +162,13 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[i][j][v] = mod_reduce(acc[i][j][v], mod);
+                    for (int v = 0; v < 4; ++v) acc[i][j][v] = (CT)mod_reduce((double)acc[i][j][v], mod);
             kacc = 0;
         }
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
-            double a[FM], b[FN];
+            CT a[FM], b[FN];
 #pragma unroll
             for (int i = 0; i < FM; ++i) a[i] = As[(wm0 + i * 16 + (lane & 15)) * PA + kr];
 #pragma unroll
@@ -151,7 +177,7 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = MT::mfma(a[i], b[j], acc[i][j]);
         }
         kacc += BK;
     }
@@ -163,10 +189,10 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gr = row0 + wm0 + i * 16 + (lane >> 4) + 4 * v;
+                const int gr = row0 + wm0 + i * 16 + MT::row(lane, v);
                 const int gc = col0 + wn0 + j * 16 + (lane & 15);
                 if (gr < M && gc < N) {
-                    const double x = mod_reduce(acc[i][j][v], mod);
+                    const double x = mod_reduce((double)acc[i][j][v], mod);
                     C[(int64_t)gr * P.ldc + gc] = from_f64<T>(x);
                     nz |= (x != 0.0);
                 }
@@ -174,19 +200,19 @@ __global__ __launch_bounds__(256) void modmm_f64_kernel(const MMArgs args) {
     if (nz && P.nzflag) *P.nzflag = P.nzgen;
 }
 
-template <typename T, int BM, int BN, int BK>
+template <typename T, typename CT, int BM, int BN, int BK>
 static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
-    PLUQ_LAUNCH((modmm_f64_kernel<T, BM, BN, BK>), dim3(total), dim3(256), 0, st, args);
+    PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK>), dim3(total), dim3(256), 0, st, args);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename CT>
 static hipError_t launch_dt(MMArgs &args, int big, int total, hipStream_t st) {
-    return big == 128 ? launch_t<T, 128, 128, 32>(args, total, st) : launch_t<T, 64, 64, 64>(args, total, st);
+    return big == 128 ? launch_t<T, CT, 128, 128, 32>(args, total, st) : launch_t<T, CT, 64, 64, 64>(args, total, st);
 }
 
-hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
-                            hipStream_t st) {
+template <typename CT>
+static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
     MMArgs args;
     int n = 0;
     int64_t tiles128 = 0;
@@ -214,11 +240,19 @@ hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, in
     args.mod.pinv = 1.0 / p;
     args.mod.half = (double)((int64_t)p / 2);
     switch (dtype) {
-    case DT_I64: return launch_dt<int64_t>(args, big, total, st);
-    case DT_F64: return launch_dt<double>(args, big, total, st);
-    case DT_I32: return launch_dt<int32_t>(args, big, total, st);
+    case DT_I64: return launch_dt<int64_t, CT>(args, big, total, st);
+    case DT_F64: return launch_dt<double, CT>(args, big, total, st);
+    case DT_I32: return launch_dt<int32_t, CT>(args, big, total, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
+    return launch_modmm<double>(dtype, probs, nprob, p, kchunk, st);
+}
+
+hipError_t launch_modmm_f32(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
+    return launch_modmm<float>(dtype, probs, nprob, p, kchunk, st);
 }
 
 }  // namespace pluq

@@ -1,0 +1,336 @@
+// INT8-limb form of MM(C, A, B) (Section 2's Schur update), exact:
+//     C <- C - sum_k A[i][k] B[k][j]   (mod p),   p <= 65536.
+//
+// Every operand a in [0, p) is moved into the window [-32896, 32639]
+// (a itself when a <= 32639, else a - p) and written as two balanced signed
+// base-256 digits, a = 256 d1 + d0 with d0, d1 in [-128, 127]; for p <= 256
+// the window is [-128, 127] and one digit suffices.  The product then splits
+// into limb products on the int8 matrix cores with int32 accumulation:
+//     A.B = 2^16 S2 + 2^8 S1 + S0,
+//     S0 = A0.B0,  S1 = A0.B1 + A1.B0,  S2 = A1.B1,
+// where every term is at most 2^14 in magnitude, so for an inner dimension
+// of at most KMAX_I8 = 4096 (one launch) |S1| < 2^27 and the recombination
+// 2^16 S2 + 2^8 S1 + S0 is below 2^43: it is formed exactly in float64,
+// subtracted from C and reduced once per output (delayed reduction,
+// Section 6).  Pivot inversion and everything outside MM stay in float64.
+//
+// Two kernels:
+//   limb_split_kernel -- writes the digit planes of the operand blocks into
+//     workspace, [rows][Kp] int8 with the inner dimension contiguous (B is
+//     transposed on the way through LDS), zero-padded to a multiple of 64.
+//   modmm_i8_kernel   -- 128 x 128 output tile per 256-thread work-group,
+//     2 x 2 waves of 64 x 64, each 2 x 2 blocks of v_mfma_i32_32x32x32_i8;
+//     the planes are staged in LDS 64 bytes of K at a time (rows padded to
+//     80 bytes so that the 16-byte fragment reads of a wave hit distinct
+//     banks) and the next panel's global loads are in flight during the
+//     current panel's matrix-core work.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace pluq {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+// ------------------------------------------------------------------ split --
+
+struct SplitArgs {
+    SplitJob job[SPLIT_MAX_JOBS];
+    int32_t count;
+    int32_t thr;   // largest residue kept as is; larger ones become a - p
+    ModP mod;
+};
+
+__device__ __forceinline__ int shifted(double a, int thr, double p) {
+    return (int)((a > (double)thr) ? a - p : a);
+}
+
+__device__ __forceinline__ void digits(int v, int &d0, int &d1) {
+    d0 = ((v + 128) & 255) - 128;
+    d1 = (v - d0) >> 8;   // exact: v - d0 is a multiple of 256
+}
+
+// Row job: source rows x K, inner dimension contiguous; thread = 8
+// consecutive entries of one row.  Transposed job: source K x rows (the
+// B operand, columns contiguous); a 64 x 64 tile per work-group goes through
+// LDS so that both the reads and the plane writes are contiguous.
+template <typename T, int NL>
+__global__ __launch_bounds__(256) void limb_split_kernel(const SplitArgs args) {
+    __shared__ int8_t tl[NL][64 * 68];
+    int ji = 0;
+#pragma unroll
+    for (int q = 1; q < SPLIT_MAX_JOBS; ++q)
+        if (q < args.count && (int)blockIdx.x >= args.job[q].blockStart) ji = q;
+    const SplitJob &J = args.job[ji];
+    const int b = blockIdx.x - J.blockStart;
+    const T *X = (const T *)J.src;
+    const double p = args.mod.p;
+    const int thr = args.thr;
+    const int tid = threadIdx.x;
+    if (!J.trans) {
+        const int64_t groups_per_row = J.Kp / 8;
+        const int64_t g = (int64_t)b * 256 + tid;
+        if (g >= (int64_t)J.rows * groups_per_row) return;
+        const int row = (int)(g / groups_per_row);
+        const int k0 = (int)(g % groups_per_row) * 8;
+        uint64_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + e;
+            const double a = (k < J.K) ? to_f64(X[(int64_t)row * J.ld + k]) : 0.0;
+            int d0, d1;
+            digits(shifted(a, thr, p), d0, d1);
+            w0 |= (uint64_t)(uint8_t)d0 << (8 * e);
+            w1 |= (uint64_t)(uint8_t)d1 << (8 * e);
+        }
+        *(uint64_t *)(J.dst0 + (int64_t)row * J.ldd + k0) = w0;
+        if (NL == 2) *(uint64_t *)(J.dst1 + (int64_t)row * J.ldd + k0) = w1;
+    } else {
+        const int tilesK = (int)(J.Kp / 64);
+        const int n0 = (b / tilesK) * 64, kb = (b % tilesK) * 64;
+        // read 64 (k) x 64 (n) entries, n contiguous
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int idx = tid + 256 * e;
+            const int kk = idx >> 6, nn = idx & 63;
+            const int k = kb + kk, n = n0 + nn;
+            const double a = (k < J.K && n < J.rows) ? to_f64(X[(int64_t)k * J.ld + n]) : 0.0;
+            int d0, d1;
+            digits(shifted(a, thr, p), d0, d1);
+            tl[0][nn * 68 + kk] = (int8_t)d0;
+            if (NL == 2) tl[NL - 1][nn * 68 + kk] = (int8_t)d1;
+        }
+        __syncthreads();
+        const int nn = tid >> 2, c = (tid & 3) * 16;
+        const int n = n0 + nn;
+        if (n < J.rows) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const int8_t *s = &tl[l][nn * 68 + c];
+                v4i w;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    w[q] = (int)((uint32_t)(uint8_t)s[4 * q] | ((uint32_t)(uint8_t)s[4 * q + 1] << 8) |
+                                 ((uint32_t)(uint8_t)s[4 * q + 2] << 16) | ((uint32_t)(uint8_t)s[4 * q + 3] << 24));
+                int8_t *d = (l == 0 ? J.dst0 : J.dst1) + (int64_t)n * J.ldd + kb + c;
+                *(v4i *)d = w;
+            }
+        }
+    }
+}
+
+template <typename T, int NL>
+static hipError_t split_t(SplitArgs &a, int total, hipStream_t st) {
+    PLUQ_LAUNCH((limb_split_kernel<T, NL>), dim3(total), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NL>
+static hipError_t split_dt(int dtype, SplitArgs &a, int total, hipStream_t st) {
+    switch (dtype) {
+    case DT_I64: return split_t<int64_t, NL>(a, total, st);
+    case DT_F64: return split_t<double, NL>(a, total, st);
+    case DT_I32: return split_t<int32_t, NL>(a, total, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int i8_limbs(double p) { return p <= 256.0 ? 1 : (p <= 65536.0 ? 2 : 0); }
+
+hipError_t launch_limb_split(int dtype, SplitJob *jobs, int njobs, double p, hipStream_t st) {
+    const int nl = i8_limbs(p);
+    if (nl == 0 || njobs <= 0 || njobs > SPLIT_MAX_JOBS) return hipErrorInvalidValue;
+    SplitArgs a;
+    a.count = njobs;
+    a.thr = nl == 1 ? 127 : 32639;
+    a.mod.p = p;
+    a.mod.pinv = 1.0 / p;
+    a.mod.half = (double)((int64_t)p / 2);
+    int total = 0;
+    for (int q = 0; q < njobs; ++q) {
+        SplitJob &J = jobs[q];
+        if (J.Kp % 64 || J.ldd % 16 || J.K > J.Kp) return hipErrorInvalidValue;
+        J.blockStart = total;
+        const int64_t blocks = J.trans ? cdiv64(J.rows, 64) * (J.Kp / 64) : cdiv64((int64_t)J.rows * (J.Kp / 8), 256);
+        total += (int)blocks;
+        a.job[q] = J;
+    }
+    if (total == 0) return hipSuccess;
+    return nl == 1 ? split_dt<1>(dtype, a, total, st) : split_dt<2>(dtype, a, total, st);
+}
+
+// ------------------------------------------------------------------- GEMM --
+
+struct I8Args {
+    void *C;
+    int64_t ldc;
+    int32_t M, N, Kp, tilesN;
+    const int8_t *a[2];
+    const int8_t *b[2];
+    int64_t lda, ldb;   // bytes between plane rows
+    int32_t *nzflag;
+    int32_t nzgen;
+    ModP mod;
+};
+
+template <typename T, int NL>
+__global__ __launch_bounds__(256) void modmm_i8_kernel(const I8Args g) {
+    constexpr int BM = 128, BN = 128, BK = 64, LDP = BK + 16;
+    constexpr int NS = NL == 2 ? 3 : 1;   // limb sums S0 (, S1, S2)
+    __shared__ __attribute__((aligned(16))) int8_t As[NL][BM * LDP];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[NL][BN * LDP];
+
+    const int tile = blockIdx.x;
+    const int row0 = (tile / g.tilesN) * BM, col0 = (tile % g.tilesN) * BN;
+    const int M = g.M, N = g.N;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+
+    v16i acc[NS][2][2];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[s][i][j][v] = 0;
+
+    // Global loads: 16 bytes per thread, plane row tid/4 (+64), chunk tid%4.
+    // Rows past M (N) are clamped to the last valid row: their products only
+    // reach outputs that are never stored.
+    const int lr = tid >> 2, lc = (tid & 3) * 16;
+    const int64_t ar0 = (int64_t)min(row0 + lr, M - 1) * g.lda + lc;
+    const int64_t ar1 = (int64_t)min(row0 + lr + 64, M - 1) * g.lda + lc;
+    const int64_t br0 = (int64_t)min(col0 + lr, N - 1) * g.ldb + lc;
+    const int64_t br1 = (int64_t)min(col0 + lr + 64, N - 1) * g.ldb + lc;
+    v4i pa[NL][2], pb[NL][2];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            pa[l][0] = *(const v4i *)(g.a[l] + ar0 + k0);
+            pa[l][1] = *(const v4i *)(g.a[l] + ar1 + k0);
+            pb[l][0] = *(const v4i *)(g.b[l] + br0 + k0);
+            pb[l][1] = *(const v4i *)(g.b[l] + br1 + k0);
+        }
+    };
+
+    const int steps = g.Kp / BK;
+    if (steps > 0) load(0);
+    for (int s = 0; s < steps; ++s) {
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            *(v4i *)&As[l][lr * LDP + lc] = pa[l][0];
+            *(v4i *)&As[l][(lr + 64) * LDP + lc] = pa[l][1];
+            *(v4i *)&Bs[l][lr * LDP + lc] = pb[l][0];
+            *(v4i *)&Bs[l][(lr + 64) * LDP + lc] = pb[l][1];
+        }
+        __syncthreads();
+        if (s + 1 < steps) load((s + 1) * BK);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            // v_mfma_i32_32x32x32_i8: lane holds row (A) / column (B) lane%32
+            // and inner indices 16*(lane/32) .. +15 of the 32-deep step.
+            const int ko = ks * 32 + (lane >> 5) * 16;
+            v4i fa[NL][2], fb[NL][2];
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    fa[l][i] = *(const v4i *)&As[l][(wm0 + 32 * i + (lane & 31)) * LDP + ko];
+                    fb[l][i] = *(const v4i *)&Bs[l][(wn0 + 32 * i + (lane & 31)) * LDP + ko];
+                }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[0][j], acc[0][i][j], 0, 0, 0);
+                    if (NL == 2) {
+                        acc[NS - 2][i][j] =
+                            __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[NL - 1][j], acc[NS - 2][i][j], 0, 0, 0);
+                        acc[NS - 2][i][j] =
+                            __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[NL - 1][i], fb[0][j], acc[NS - 2][i][j], 0, 0, 0);
+                        acc[NS - 1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[NL - 1][i], fb[NL - 1][j],
+                                                                                   acc[NS - 1][i][j], 0, 0, 0);
+                    }
+                }
+        }
+    }
+
+    // Epilogue: element v of a 32 x 32 block sits at row
+    // 8*(v/4) + 4*(lane/32) + v%4 and column lane%32.
+    const ModP mod = g.mod;
+    T *C = (T *)g.C;
+    bool nz = false;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int gc = col0 + wn0 + 32 * j + (lane & 31);
+            double cv[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int gr = row0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                cv[v] = to_f64(C[(int64_t)min(gr, M - 1) * g.ldc + min(gc, N - 1)]);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int gr = row0 + wm0 + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                double t = (double)acc[0][i][j][v];
+                if (NL == 2) t += 256.0 * (double)acc[NS - 2][i][j][v] + 65536.0 * (double)acc[NS - 1][i][j][v];
+                if (gr < M && gc < N) {
+                    const double x = mod_reduce(cv[v] - t, mod);
+                    C[(int64_t)gr * g.ldc + gc] = from_f64<T>(x);
+                    nz |= (x != 0.0);
+                }
+            }
+        }
+    if (nz && g.nzflag) *g.nzflag = g.nzgen;
+}
+
+template <typename T, int NL>
+static hipError_t i8_t(I8Args &a, int total, hipStream_t st) {
+    PLUQ_LAUNCH((modmm_i8_kernel<T, NL>), dim3(total), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NL>
+static hipError_t i8_dt(int dtype, I8Args &a, int total, hipStream_t st) {
+    switch (dtype) {
+    case DT_I64: return i8_t<int64_t, NL>(a, total, st);
+    case DT_F64: return i8_t<double, NL>(a, total, st);
+    case DT_I32: return i8_t<int32_t, NL>(a, total, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_modmm_i8(int dtype, void *C, int64_t ldc, int M, int N, int Kp, const int8_t *const a[2],
+                           const int8_t *const b[2], int64_t lda, int64_t ldb, double p, int32_t *nzflag,
+                           int32_t nzgen, hipStream_t st) {
+    const int nl = i8_limbs(p);
+    if (nl == 0 || Kp % 64 || Kp > KMAX_I8 || lda % 16 || ldb % 16) return hipErrorInvalidValue;
+    if (M <= 0 || N <= 0) return hipSuccess;
+    I8Args g;
+    g.C = C;
+    g.ldc = ldc;
+    g.M = M;
+    g.N = N;
+    g.Kp = Kp;
+    g.tilesN = (int)cdiv64(N, 128);
+    g.a[0] = a[0];
+    g.a[1] = nl == 2 ? a[1] : a[0];
+    g.b[0] = b[0];
+    g.b[1] = nl == 2 ? b[1] : b[0];
+    g.lda = lda;
+    g.ldb = ldb;
+    g.nzflag = nzflag;
+    g.nzgen = nzgen;
+    g.mod.p = p;
+    g.mod.pinv = 1.0 / p;
+    g.mod.half = (double)((int64_t)p / 2);
+    const int total = (int)(cdiv64(M, 128) * g.tilesN);
+    return nl == 1 ? i8_dt<1>(dtype, g, total, st) : i8_dt<2>(dtype, g, total, st);
+}
+
+}  // namespace pluq

@@ -31,6 +31,35 @@ constexpr int MM_MAX_PROBLEMS = 4;
 // be accumulated before a reduction (multiple of 16, >= 16).
 hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
                             hipStream_t st);
+// FP32 matrix-core form (p < 2^11): kchunk products between reductions,
+// kchunk * (p/2)^2 + p < 2^24.
+hipError_t launch_modmm_f32(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
+                            hipStream_t st);
+
+// INT8-limb form (p <= 65536).  Number of signed 8-bit digits per operand
+// (1 for p <= 256, 2 for p <= 65536, 0 when the form cannot be exact).
+int i8_limbs(double p);
+// One block of digit planes to produce: the source block is rows x K
+// (trans = 0, inner dimension contiguous: an A operand) or K x rows
+// (trans = 1, a B operand); the planes dst0 / dst1 are [rows][ldd] int8 and
+// receive columns [0, Kp) (Kp a multiple of 64; entries k >= K are zero).
+struct SplitJob {
+    const void *src;
+    int64_t ld;
+    int32_t rows, K, Kp, trans;
+    int8_t *dst0, *dst1;
+    int64_t ldd;
+    int32_t blockStart;   // filled by the launcher
+};
+constexpr int SPLIT_MAX_JOBS = 4;
+constexpr int KMAX_I8 = 4096;   // inner dimension of one INT8 launch
+hipError_t launch_limb_split(int dtype, SplitJob *jobs, int njobs, double p, hipStream_t st);
+// C (M x N, ldc) <- C - sum over the Kp inner positions of the digit planes
+// a (M rows of lda bytes) and b (N rows of ldb bytes), mod p; nzflag as in
+// MMProblem.  Kp <= KMAX_I8, a multiple of 64.
+hipError_t launch_modmm_i8(int dtype, void *C, int64_t ldc, int M, int N, int Kp, const int8_t *const a[2],
+                           const int8_t *const b[2], int64_t lda, int64_t ldb, double p, int32_t *nzflag,
+                           int32_t nzgen, hipStream_t st);
 
 // Left lower unit TRSM leaf: B (nb x ncols, ldb) <- L^{-1} B, nb <= 64.
 hipError_t launch_trsm_llu_leaf(int dtype, const void *L, int64_t ldl, int nb, void *B,

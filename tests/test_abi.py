@@ -65,3 +65,24 @@ def test_rank_profile_queries_host():
     assert rr.tolist() == [0, 2] and cc.tolist() == [0, 1]
     rows, cols = pl.pluq_leading_rank_profiles(P, Q, 2, 2, 2)
     assert rows.tolist() == [0] and cols.tolist() == [1]
+
+
+def test_form_bounds_host_checks():
+    """The exactness bounds of the forms are checked before any device work
+    (an empty problem with null pointers reaches no kernel)."""
+    import ctypes
+    import paper_1301_4438_amd as pl
+    L = pl.load()
+    ok, unsup = pl.PLUQ_OK, 4
+    def mm(p, form):
+        return L.pluq_modmm(0, 0, 0, None, 1, None, 1, None, 1, 1, p, form, None, 0, None)
+    assert mm(65521, 1) == ok and mm(65536, 1) == ok and mm(65537, 1) == unsup
+    assert mm(251, 2) == ok and mm(2039, 2) == ok and mm(2053, 2) == unsup
+    assert mm((1 << 25) - 1, 0) == ok and mm((1 << 25) + 1, 0) == unsup and mm(65537, 0) == ok
+    # the INT8 form needs digit-plane workspace on top of the FP64 one
+    o8, o64 = pl._opts("int8"), pl._opts("fp64")
+    w8 = L.pluq_workspace_size(1024, 1024, 1, 65521, ctypes.byref(o8))
+    w64 = L.pluq_workspace_size(1024, 1024, 1, 65521, ctypes.byref(o64))
+    assert w8 >= w64 + 2 * 2048 * 1024
+    assert L.pluq_modmm_workspace_size(100, 200, 5000, 1) >= 2 * 300 * 4096
+    assert L.pluq_modmm_workspace_size(100, 200, 5000, 0) == 0
