@@ -93,6 +93,8 @@ typedef struct {
     int32_t validate_entries; /* non-zero: scan A for entries outside [0,p) first */
     int32_t cutoff_override;  /* > 0: base-case tiles at most this many rows and columns (tuning only) */
     int32_t trsm_leaf_override; /* > 0: order of the TRSM leaf solves, <= 64 (tuning only) */
+    int32_t batch_panel;        /* batched form: panel width 8 or 16 (0: 16; tuning only) */
+    int32_t batch_groups;       /* batched form: persistent work-groups per compute unit (0: 2) */
 } pluq_opts;
 
 /* Human-readable name of a status code (static storage). */
@@ -150,17 +152,39 @@ pluq_status pluq_leading_rank_profiles(int64_t m, int64_t n, int64_t r,
                                        int64_t *cols, int64_t *count);
 
 /*
- * Batched PLUQ: `batch` independent matrices, each processed as by
- * pluq_modp, in one persistent launch on `stream`.
- *   m, n, lda        host arrays of length batch.
- *   dA, dP, dQ       host arrays of `batch` device pointers.
- *   d_r              device int64 array of length batch; receives the ranks.
- *   dWork/work_bytes device workspace >= pluq_batched_workspace_size(...).
- * The call does not synchronise the stream; d_r is valid once the stream
- * reaches it.  Errors as for pluq_modp.
+ * Batched PLUQ: `batch` independent matrices, each decomposed exactly as by
+ * pluq_modp (same P, Q, r and packed factors), in one persistent kernel
+ * launch on `stream` with every pivoting decision taken on the device.
+ *   m, n, lda        host arrays of length batch; 0 <= m, n <= 512.
+ *   dA, dP, dQ       host arrays of `batch` device pointers (A in place,
+ *                    P of length m[b], Q of length n[b], int64).
+ *   d_r              device int64 array of length batch; receives the ranks
+ *                    (-1 for a matrix whose internal self-check failed).
+ *   dWork/work_bytes device workspace >= pluq_batched_workspace_size(...),
+ *                    256-byte aligned: a descriptor table and a backup copy
+ *                    of every matrix.
+ * Only the FP64 form's arithmetic is used (the updates are rank-16 and too
+ * small for the matrix cores); opts may select the panel width and the
+ * number of resident work-groups.
+ *
+ * pluq_modp_batched = pluq_batched_prepare + pluq_batched_run.
+ *   prepare  validates the arguments and writes the descriptor table into
+ *            dWork (synchronous host-to-device copy; no kernel).
+ *   run      enqueues the single kernel on `stream` and returns: it makes
+ *            no host-device transfer and no synchronisation, so it may be
+ *            captured into a HIP graph and replayed; every replay works on
+ *            the matrices the descriptors point to, in place.
+ * Errors as for pluq_modp; PLUQ_ERR_UNSUPPORTED for a dimension above 512.
  */
 size_t pluq_batched_workspace_size(int64_t batch, const int64_t *m, const int64_t *n,
                                    pluq_dtype dt, uint64_t p, const pluq_opts *opts);
+pluq_status pluq_batched_prepare(int64_t batch, const int64_t *m, const int64_t *n,
+                                 void *const *dA, const int64_t *lda, pluq_dtype dt,
+                                 uint64_t p, int64_t *const *dP, int64_t *const *dQ,
+                                 int64_t *d_r, const pluq_opts *opts, void *dWork,
+                                 size_t work_bytes);
+pluq_status pluq_batched_run(int64_t batch, pluq_dtype dt, uint64_t p, const pluq_opts *opts,
+                             void *dWork, size_t work_bytes, void *stream);
 pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n,
                               void *const *dA, const int64_t *lda, pluq_dtype dt,
                               uint64_t p, int64_t *const *dP, int64_t *const *dQ,

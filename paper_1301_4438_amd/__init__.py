@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpluq.so")
 
 PLUQ_OK = 0
+PLUQ_ERR_UNSUPPORTED = 4
 STATUS = {0: "ok", 1: "invalid argument", 2: "modulus outside [2, 2^26)", 3: "entry outside [0, p)",
           4: "form cannot be exact for this modulus", 5: "host allocation failed",
           6: "device (HIP) error", 7: "workspace too small"}
@@ -38,7 +39,8 @@ class PluqError(RuntimeError):
 
 class pluq_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("validate_entries", ctypes.c_int32),
-                ("cutoff_override", ctypes.c_int32), ("trsm_leaf_override", ctypes.c_int32)]
+                ("cutoff_override", ctypes.c_int32), ("trsm_leaf_override", ctypes.c_int32),
+                ("batch_panel", ctypes.c_int32), ("batch_groups", ctypes.c_int32)]
 
 
 class pluq_kernel_stat(ctypes.Structure):
@@ -75,6 +77,12 @@ def load():
     L.pluq_modp_batched.argtypes = [_i64, _i64p, _i64p, ctypes.POINTER(_vp), _i64p, ctypes.c_int, _u64,
                                     ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(pluq_opts),
                                     _vp, ctypes.c_size_t, _vp]
+    L.pluq_batched_prepare.restype = ctypes.c_int
+    L.pluq_batched_prepare.argtypes = [_i64, _i64p, _i64p, ctypes.POINTER(_vp), _i64p, ctypes.c_int, _u64,
+                                       ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(pluq_opts),
+                                       _vp, ctypes.c_size_t]
+    L.pluq_batched_run.restype = ctypes.c_int
+    L.pluq_batched_run.argtypes = [_i64, ctypes.c_int, _u64, ctypes.POINTER(pluq_opts), _vp, ctypes.c_size_t, _vp]
     L.pluq_modmm_workspace_size.restype = ctypes.c_size_t
     L.pluq_modmm_workspace_size.argtypes = [_i64, _i64, _i64, ctypes.c_int32]
     L.pluq_modmm.restype = ctypes.c_int
@@ -105,17 +113,30 @@ def _dtype_code(t) -> int:
     return m[t.dtype]
 
 
+def _ld(t) -> int:
+    """Row stride of a row-major 2-D tensor; a single row's is immaterial
+    (torch may report any stride for a dimension of size one)."""
+    return t.stride(0) if t.shape[0] > 1 else max(1, t.shape[1])
+
+
+def _torch():
+    import torch
+    return torch
+
+
 def _stream(t):
     import torch
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _opts(form="fp64", validate=False, cutoff=0, trsm_leaf=0):
+def _opts(form="fp64", validate=False, cutoff=0, trsm_leaf=0, batch_panel=0, batch_groups=0):
     o = pluq_opts()
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.validate_entries = int(bool(validate))
     o.cutoff_override = int(cutoff)
     o.trsm_leaf_override = int(trsm_leaf)
+    o.batch_panel = int(batch_panel)
+    o.batch_groups = int(batch_groups)
     return o
 
 
@@ -157,7 +178,7 @@ def pluq_modp(A, p: int, P, Q, opts=None, work=None):
     Returns r."""
     L = load()
     m, n = A.shape
-    lda = A.stride(0) if m > 0 else max(1, n)
+    lda = A.stride(0) if m > 1 else max(1, n)
     if A.dim() != 2 or (m > 0 and n > 1 and A.stride(1) != 1):
         raise ValueError("A must be a row-major 2-D tensor with unit column stride")
     if m == 0 or n == 0:
@@ -202,6 +223,76 @@ def pluq_leading_rank_profiles(P, Q, r, k, t):
     return rows[:cnt.value], cols[:cnt.value]
 
 
+class BatchedCall:
+    """Arguments of one batched decomposition, marshalled once: the device
+    tensors (in place), P and Q per matrix, the rank vector and the
+    workspace.  `prepare()` writes the descriptor table (synchronous),
+    `run()` enqueues the single kernel (capturable into a HIP graph)."""
+
+    def __init__(self, mats, p: int, Ps, Qs, d_r, opts=None, work=None):
+        import numpy as np
+        self.L = load()
+        self.mats, self.Ps, self.Qs, self.d_r = list(mats), list(Ps), list(Qs), d_r
+        self.p = int(p)
+        self.opts = opts
+        b = len(self.mats)
+        self.batch = b
+        if len(self.Ps) != b or len(self.Qs) != b or d_r.numel() != b or d_r.dtype != _torch().int64:
+            raise ValueError("need one P, one Q and one int64 rank slot per matrix")
+        dts = {_dtype_code(a) for a in self.mats}
+        if len(dts) > 1:
+            raise TypeError("all matrices of a batch must share one element type")
+        self.dt = dts.pop() if dts else 1
+        for a in self.mats:
+            if a.dim() != 2 or (a.shape[0] > 0 and a.shape[1] > 1 and a.stride(1) != 1):
+                raise ValueError("matrices must be row-major 2-D tensors with unit column stride")
+        self.m = np.array([a.shape[0] for a in self.mats], np.int64)
+        self.n = np.array([a.shape[1] for a in self.mats], np.int64)
+        # a single row's leading dimension is immaterial (torch may report any
+        # stride for a dimension of size one)
+        self.lda = np.array([a.stride(0) if a.shape[0] > 1 else max(1, a.shape[1]) for a in self.mats], np.int64)
+        self.pa = (_vp * max(b, 1))(*[a.data_ptr() for a in self.mats])
+        self.pp = (_vp * max(b, 1))(*[t.data_ptr() for t in self.Ps])
+        self.pq = (_vp * max(b, 1))(*[t.data_ptr() for t in self.Qs])
+        o = ctypes.byref(opts) if opts else None
+        need = int(self.L.pluq_batched_workspace_size(b, self.m.ctypes.data_as(_i64p), self.n.ctypes.data_as(_i64p),
+                                                      self.dt, self.p, o))
+        if b and need == 0:
+            raise PluqError(PLUQ_ERR_UNSUPPORTED, "pluq_batched_workspace_size")
+        dev = self.mats[0].device if b else "cuda"
+        self.work = work if work is not None else _torch().empty(max(need, 256), dtype=_torch().uint8, device=dev)
+
+    def prepare(self):
+        o = ctypes.byref(self.opts) if self.opts else None
+        st = self.L.pluq_batched_prepare(self.batch, self.m.ctypes.data_as(_i64p), self.n.ctypes.data_as(_i64p),
+                                         self.pa, self.lda.ctypes.data_as(_i64p), self.dt, self.p, self.pp, self.pq,
+                                         ctypes.c_void_p(self.d_r.data_ptr()), o,
+                                         ctypes.c_void_p(self.work.data_ptr()), self.work.numel())
+        _check(st, "pluq_batched_prepare")
+        return self
+
+    def run(self, stream=None):
+        o = ctypes.byref(self.opts) if self.opts else None
+        s = stream if stream is not None else (_stream(self.mats[0]) if self.batch else None)
+        st = self.L.pluq_batched_run(self.batch, self.dt, self.p, o, ctypes.c_void_p(self.work.data_ptr()),
+                                     self.work.numel(), s)
+        _check(st, "pluq_batched_run")
+
+
+def pluq_modp_batched(mats, p: int, Ps, Qs, d_r, opts=None):
+    """In-place decomposition of every 2-D device tensor in `mats` (one
+    element type, m, n <= 512) in one persistent launch; ranks into the
+    device int64 tensor d_r.  Asynchronous."""
+    call = BatchedCall(mats, p, Ps, Qs, d_r, opts)
+    o = ctypes.byref(opts) if opts else None
+    st = call.L.pluq_modp_batched(call.batch, call.m.ctypes.data_as(_i64p), call.n.ctypes.data_as(_i64p), call.pa,
+                                  call.lda.ctypes.data_as(_i64p), call.dt, call.p, call.pp, call.pq,
+                                  ctypes.c_void_p(d_r.data_ptr()), o, ctypes.c_void_p(call.work.data_ptr()),
+                                  call.work.numel(), _stream(mats[0]) if call.batch else None)
+    _check(st, "pluq_modp_batched")
+    return call
+
+
 def pluq_modmm(C, A, B, p: int, form="fp64", work=None):
     """C <- C - A B mod p on device tensors (in place, asynchronous)."""
     L = load()
@@ -219,8 +310,8 @@ def pluq_modmm(C, A, B, p: int, form="fp64", work=None):
     need = int(L.pluq_modmm_workspace_size(m, n, k, fcode))
     if work is None and need:
         work = _workspace(C.device, need)
-    st = L.pluq_modmm(m, n, k, ctypes.c_void_p(C.data_ptr()), C.stride(0), ctypes.c_void_p(A.data_ptr()),
-                      A.stride(0), ctypes.c_void_p(B.data_ptr()), B.stride(0), dt, p, fcode,
+    st = L.pluq_modmm(m, n, k, ctypes.c_void_p(C.data_ptr()), _ld(C), ctypes.c_void_p(A.data_ptr()),
+                      _ld(A), ctypes.c_void_p(B.data_ptr()), _ld(B), dt, p, fcode,
                       ctypes.c_void_p(work.data_ptr() if work is not None else 0),
                       work.numel() if work is not None else 0, _stream(C))
     _check(st, "pluq_modmm")
@@ -238,8 +329,8 @@ def pluq_trsm(side: int, T, B, p: int, form="fp64"):
     dt = _dtype_code(B)
     fcode = FORMS[form] if isinstance(form, str) else int(form)
     work = _workspace(B.device, int(L.pluq_trsm_workspace_size(r, dt)))
-    st = L.pluq_trsm(side, r, other, ctypes.c_void_p(T.data_ptr()), T.stride(0), ctypes.c_void_p(B.data_ptr()),
-                     B.stride(0), dt, p, fcode, ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(B))
+    st = L.pluq_trsm(side, r, other, ctypes.c_void_p(T.data_ptr()), _ld(T), ctypes.c_void_p(B.data_ptr()),
+                     _ld(B), dt, p, fcode, ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(B))
     _check(st, "pluq_trsm")
 
 

@@ -306,19 +306,111 @@ pluq_status pluq_leading_rank_profiles(int64_t m, int64_t n, int64_t r, const in
     return PLUQ_OK;
 }
 
+// Batched workspace: descriptor table, then one backup copy per matrix.
+static size_t batched_layout(int64_t batch, const int64_t *m, const int64_t *n, size_t esz,
+                             std::vector<int64_t> *woff) {
+    size_t off = align_up((size_t)batch * sizeof(BatchDesc));
+    const size_t base = off;
+    if (woff) woff->resize((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) {
+        if (woff) (*woff)[(size_t)b] = (int64_t)(off - base);
+        off += align_up((size_t)std::max<int64_t>(m[b], 0) * (size_t)std::max<int64_t>(n[b], 0) * esz);
+    }
+    return off;
+}
+
+static pluq_status batched_check(int64_t batch, const int64_t *m, const int64_t *n, pluq_dtype dt, uint64_t p,
+                                 const pluq_opts *opts) {
+    if (batch < 0 || batch > INT32_MAX || esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (batch > 0 && (!m || !n)) return PLUQ_ERR_ARG;
+    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
+    if (fp64_kchunk(p) < 16) return PLUQ_ERR_UNSUPPORTED;
+    if (opts) {
+        if (opts->batch_panel != 0 && opts->batch_panel != 8 && opts->batch_panel != 16) return PLUQ_ERR_ARG;
+        if (opts->batch_groups < 0 || opts->batch_groups > 8) return PLUQ_ERR_ARG;
+    }
+    for (int64_t b = 0; b < batch; ++b) {
+        if (m[b] < 0 || n[b] < 0) return PLUQ_ERR_ARG;
+        if (m[b] > BATCH_MAX_DIM || n[b] > BATCH_MAX_DIM) return PLUQ_ERR_UNSUPPORTED;
+    }
+    return PLUQ_OK;
+}
+
 size_t pluq_batched_workspace_size(int64_t batch, const int64_t *m, const int64_t *n, pluq_dtype dt, uint64_t p,
                                    const pluq_opts *opts) {
-    (void)batch; (void)m; (void)n; (void)dt; (void)p; (void)opts;
-    return 0;
+    if (batched_check(batch, m, n, dt, p, opts) != PLUQ_OK) return 0;
+    return std::max<size_t>(ALIGN, batched_layout(batch, m, n, esize(dt), nullptr));
+}
+
+pluq_status pluq_batched_prepare(int64_t batch, const int64_t *m, const int64_t *n, void *const *dA,
+                                 const int64_t *lda, pluq_dtype dt, uint64_t p, int64_t *const *dP,
+                                 int64_t *const *dQ, int64_t *d_r, const pluq_opts *opts, void *dWork,
+                                 size_t work_bytes) {
+    pluq_status s = batched_check(batch, m, n, dt, p, opts);
+    if (s != PLUQ_OK) return s;
+    if (batch == 0) return PLUQ_OK;
+    if (!dA || !lda || !dP || !dQ || !d_r || !dWork) return PLUQ_ERR_ARG;
+    if ((uintptr_t)dWork % ALIGN) return PLUQ_ERR_ARG;
+    std::vector<int64_t> woff;
+    const size_t need = batched_layout(batch, m, n, esize(dt), &woff);
+    if (work_bytes < need) return PLUQ_ERR_WORKSPACE;
+    for (int64_t b = 0; b < batch; ++b) {
+        if (m[b] > 0 && n[b] > 0 && (!dA[b] || lda[b] < n[b])) return PLUQ_ERR_ARG;
+        if ((m[b] > 0 && !dP[b]) || (n[b] > 0 && !dQ[b])) return PLUQ_ERR_ARG;
+    }
+    // largest work first: the persistent work-groups take them round-robin
+    std::vector<int64_t> order((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) order[(size_t)b] = b;
+    auto cost = [&](int64_t b) { return (double)m[b] * (double)n[b] * (double)std::min(m[b], n[b]); };
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost(x) > cost(y); });
+    std::vector<BatchDesc> desc((size_t)batch);
+    for (int64_t q = 0; q < batch; ++q) {
+        const int64_t b = order[(size_t)q];
+        BatchDesc &d = desc[(size_t)q];
+        d.A = dA[b];
+        d.lda = std::max<int64_t>(lda[b], 1);
+        d.P = dP[b];
+        d.Q = dQ[b];
+        d.R = d_r + b;
+        d.woff = woff[(size_t)b];
+        d.m = (int32_t)m[b];
+        d.n = (int32_t)n[b];
+    }
+    if (hipMemcpy(dWork, desc.data(), desc.size() * sizeof(BatchDesc), hipMemcpyHostToDevice) != hipSuccess)
+        return PLUQ_ERR_DEVICE;
+    return PLUQ_OK;
+}
+
+pluq_status pluq_batched_run(int64_t batch, pluq_dtype dt, uint64_t p, const pluq_opts *opts, void *dWork,
+                             size_t work_bytes, void *stream) {
+    if (batch < 0 || batch > INT32_MAX || esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
+    if (fp64_kchunk(p) < 16) return PLUQ_ERR_UNSUPPORTED;
+    if (batch == 0) return PLUQ_OK;
+    if (!dWork || (uintptr_t)dWork % ALIGN || work_bytes < align_up((size_t)batch * sizeof(BatchDesc)))
+        return PLUQ_ERR_ARG;
+    const int kb = (opts && opts->batch_panel) ? opts->batch_panel : 16;
+    const int per_cu = (opts && opts->batch_groups) ? opts->batch_groups : 2;
+    if ((kb != 8 && kb != 16) || per_cu < 1 || per_cu > 8) return PLUQ_ERR_ARG;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return PLUQ_ERR_DEVICE;
+    const int grid = (int)std::min<int64_t>(batch, (int64_t)cus * per_cu);
+    char *w = (char *)dWork;
+    const hipError_t e = launch_batched_pluq((int)dt, kb, (const BatchDesc *)w, (int32_t)batch,
+                                             w + align_up((size_t)batch * sizeof(BatchDesc)), (double)p, grid,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? PLUQ_OK : PLUQ_ERR_DEVICE;
 }
 
 pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n, void *const *dA,
                               const int64_t *lda, pluq_dtype dt, uint64_t p, int64_t *const *dP,
                               int64_t *const *dQ, int64_t *d_r, const pluq_opts *opts, void *dWork,
                               size_t work_bytes, void *stream) {
-    (void)batch; (void)m; (void)n; (void)dA; (void)lda; (void)dt; (void)p; (void)dP; (void)dQ; (void)d_r;
-    (void)opts; (void)dWork; (void)work_bytes; (void)stream;
-    return PLUQ_ERR_UNSUPPORTED;
+    pluq_status s = pluq_batched_prepare(batch, m, n, dA, lda, dt, p, dP, dQ, d_r, opts, dWork, work_bytes);
+    if (s != PLUQ_OK) return s;
+    return pluq_batched_run(batch, dt, p, opts, dWork, work_bytes, stream);
 }
 
 size_t pluq_modmm_workspace_size(int64_t m, int64_t n, int64_t k, int32_t form) {

@@ -61,6 +61,21 @@ hipError_t launch_modmm_i8(int dtype, void *C, int64_t ldc, int M, int N, int Kp
                            const int8_t *const b[2], int64_t lda, int64_t ldb, double p, int32_t *nzflag,
                            int32_t nzgen, hipStream_t st);
 
+// Batched form: one descriptor per matrix (m, n <= BATCH_MAX_DIM).  W is the
+// backup copy of the matrix (m x n dense, at wbase + woff); R receives the
+// rank (-1 when a self-check fails).
+constexpr int BATCH_MAX_DIM = 512;
+struct BatchDesc {
+    void *A;
+    int64_t lda;
+    int64_t *P, *Q, *R;
+    int64_t woff;
+    int32_t m, n;
+};
+// kb: panel width (8 or 16); grid: persistent work-groups.
+hipError_t launch_batched_pluq(int dtype, int kb, const BatchDesc *desc, int32_t batch, char *wbase,
+                               double p, int grid, hipStream_t st);
+
 // Left lower unit TRSM leaf: B (nb x ncols, ldb) <- L^{-1} B, nb <= 64.
 hipError_t launch_trsm_llu_leaf(int dtype, const void *L, int64_t ldl, int nb, void *B,
                                 int64_t ldb, int64_t ncols, double p, int kchunk,
