@@ -389,8 +389,8 @@ pluq_status pluq_batched_run(int64_t batch, pluq_dtype dt, uint64_t p, const plu
     if (batch == 0) return PLUQ_OK;
     if (!dWork || (uintptr_t)dWork % ALIGN || work_bytes < align_up((size_t)batch * sizeof(BatchDesc)))
         return PLUQ_ERR_ARG;
-    const int kb = (opts && opts->batch_panel) ? opts->batch_panel : 16;
-    const int per_cu = (opts && opts->batch_groups) ? opts->batch_groups : 2;
+    const int kb = (opts && opts->batch_panel) ? opts->batch_panel : 8;
+    const int per_cu = (opts && opts->batch_groups) ? opts->batch_groups : (kb == 8 ? 4 : 2);
     if ((kb != 8 && kb != 16) || per_cu < 1 || per_cu > 8) return PLUQ_ERR_ARG;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||

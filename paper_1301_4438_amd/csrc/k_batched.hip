@@ -68,6 +68,42 @@ __device__ __forceinline__ double sym(double v, const ModP &m) { return to_sym(v
 
 // ----------------------------------------------------------------- LU ----
 
+// Inverse of a non-zero canonical residue by Fermat's little theorem,
+// a^(p-2) mod p, square-and-multiply on exact float64 products: a fixed,
+// wave-uniform sequence of about 2 log2(p) modular products, shorter in
+// latency than the Euclidean algorithm's chain of integer divisions.
+__device__ __forceinline__ double inv_fermat(double a, const ModP &mod) {
+    uint32_t e = (uint32_t)mod.p - 2u;
+    double r = 1.0, b = a;
+    while (e) {
+        if (e & 1u) r = mod_reduce(r * b, mod);
+        b = mod_reduce(b * b, mod);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Copy of an m x n block between two row-major arrays, eight loads in
+// flight per thread before the stores.
+template <typename T>
+__device__ void copy_block(const T *src, int64_t lds, T *dst, int64_t ldd, int m, int n) {
+    const int tid = threadIdx.x;
+    const int total = m * n;
+    for (int e0 = tid; e0 < total; e0 += 8 * BT) {
+        T v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = e0 + j * BT;
+            if (e < total) v[j] = src[(int64_t)(e / n) * lds + e % n];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = e0 + j * BT;
+            if (e < total) dst[(int64_t)(e / n) * ldd + e % n] = v[j];
+        }
+    }
+}
+
 // Elimination without pivoting of the m x n matrix at A (in place), blocked
 // by KB columns.  r_known < 0: optimistic, stop at the first zero pivot and
 // succeed iff the trailing block is zero there; r_known >= 0: exactly that
@@ -75,6 +111,7 @@ __device__ __forceinline__ double sym(double v, const ModP &m) { return to_sym(v
 // or -1 on failure.
 template <typename T, int KB>
 __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const ModP &mod, LuMem<KB> &L) {
+    constexpr int RSTEP = BT / KB;   // panel rows per pass of the work-group
     const int tid = threadIdx.x;
     const int mn = min(m, n);
     const int rmax = r_known >= 0 ? r_known : mn;
@@ -96,9 +133,20 @@ __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const Mo
         }
         const int kb = min(KB, mn - s);
         const int pr = m - s;
-        for (int e = tid; e < pr * kb; e += BT) {
-            const int i = e / kb, t = e % kb;
-            L.pan[i * KB + t] = (int32_t)to_f64(A[(int64_t)(s + i) * lda + s + t]);
+        const int pt = tid % KB, pi0 = tid / KB;
+        // panel load: thread (pi0, pt) takes rows pi0, pi0 + RSTEP, ...
+        for (int ib = pi0; ib < pr; ib += 8 * RSTEP) {
+            double v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = ib + j * RSTEP;
+                v[j] = (i < pr && pt < kb) ? to_f64(A[(int64_t)(s + i) * lda + s + pt]) : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = ib + j * RSTEP;
+                if (i < pr) L.pan[i * KB + pt] = (int32_t)v[j];
+            }
         }
         __syncthreads();
         const int tlim = min(kb, rmax - s);
@@ -109,7 +157,7 @@ __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const Mo
                 kbe = t;
                 break;
             }
-            const double inv = mod_inv(piv, mod);
+            const double inv = inv_fermat(piv, mod);
             for (int i = t + 1 + tid; i < pr; i += BT) {
                 const double l = mod_reduce((double)L.pan[i * KB + t] * inv, mod);
                 L.pan[i * KB + t] = (int32_t)l;
@@ -129,41 +177,67 @@ __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const Mo
                 const int i = kbe + e / (kb - kbe), u = kbe + e % (kb - kbe);
                 nz |= L.pan[i * KB + u] != 0;
             }
-        for (int e = tid; e < pr * kb; e += BT) {
-            const int i = e / kb, t = e % kb;
-            A[(int64_t)(s + i) * lda + s + t] = from_f64<T>((double)L.pan[i * KB + t]);
-        }
+        if (pt < kb)
+            for (int i = pi0; i < pr; i += RSTEP) A[(int64_t)(s + i) * lda + s + pt] = from_f64<T>((double)L.pan[i * KB + pt]);
         // U rows s .. s+kbe-1 right of the panel: x <- L11^{-1} x per column
         const int c0 = s + kb, W = n - c0;
         for (int c = tid; c < W; c += BT) {
             double xs[KB];
 #pragma unroll
+            for (int t = 0; t < KB; ++t)
+                if (t < kbe) xs[t] = to_f64(A[(int64_t)(s + t) * lda + c0 + c]);
+#pragma unroll
             for (int t = 0; t < KB; ++t) {
                 if (t < kbe) {
-                    double acc = to_f64(A[(int64_t)(s + t) * lda + c0 + c]);
+                    double acc = xs[t];
 #pragma unroll
                     for (int u = 0; u < t; ++u) acc = fma(-sym((double)L.pan[t * KB + u], mod), xs[u], acc);
                     const double x = mod_reduce(acc, mod);
-                    A[(int64_t)(s + t) * lda + c0 + c] = from_f64<T>(x);
                     L.urow[t * BMAX + c] = (int32_t)x;
                     xs[t] = sym(x, mod);
                 }
             }
-        }
-        __syncthreads();
-        // trailing update of rows s+kbe .., columns c0 ..
-        const int R = m - s - kbe;
-        for (int e = tid; e < R * W; e += BT) {
-            const int i = e / W, c = e % W;
-            T *a = &A[(int64_t)(s + kbe + i) * lda + c0 + c];
-            double acc = to_f64(*a);
 #pragma unroll
             for (int t = 0; t < KB; ++t)
-                if (t < kbe)
-                    acc = fma(-sym((double)L.pan[(kbe + i) * KB + t], mod), sym((double)L.urow[t * BMAX + c], mod), acc);
-            const double x = mod_reduce(acc, mod);
-            *a = from_f64<T>(x);
-            if (kbe < kb) nz |= (x != 0.0);
+                if (t < kbe) A[(int64_t)(s + t) * lda + c0 + c] = from_f64<T>((double)L.urow[t * BMAX + c]);
+        }
+        __syncthreads();
+        // trailing update of rows s+kbe .., columns c0 ..: each thread owns a
+        // column (its U entries in registers) and a set of rows, eight rows
+        // loaded before any is written
+        const int R = m - s - kbe;
+        if (R > 0 && W > 0) {
+            const int tpc = W >= BT ? 1 : BT / W;   // threads per column
+            if (tid < (W >= BT ? BT : W * tpc)) {
+                const int g = W >= BT ? 0 : tid / W;
+                for (int c = (W >= BT ? tid : tid % W); c < W; c += BT) {
+                    double u[KB];
+#pragma unroll
+                    for (int t = 0; t < KB; ++t) u[t] = (t < kbe) ? sym((double)L.urow[t * BMAX + c], mod) : 0.0;
+                    for (int ib = g; ib < R; ib += 8 * tpc) {
+                        double a[8];
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int i = ib + j * tpc;
+                            a[j] = (i < R) ? to_f64(A[(int64_t)(s + kbe + i) * lda + c0 + c]) : 0.0;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int i = ib + j * tpc;
+                            if (i < R) {
+                                double acc = a[j];
+                                const int32_t *lrow = &L.pan[(kbe + i) * KB];
+#pragma unroll
+                                for (int t = 0; t < KB; ++t)
+                                    if (t < kbe) acc = fma(-sym((double)lrow[t], mod), u[t], acc);
+                                const double x = mod_reduce(acc, mod);
+                                A[(int64_t)(s + kbe + i) * lda + c0 + c] = from_f64<T>(x);
+                                if (kbe < kb) nz |= (x != 0.0);
+                            }
+                        }
+                    }
+                }
+            }
         }
         nz = __syncthreads_or(nz);
         if (kbe < kb) {
@@ -209,7 +283,7 @@ __device__ int rpm_search(T *A, int64_t lda, int m, int n, const ModP &mod, RpmM
             const int jc = sred[0];
             __syncthreads();
             if (jc == INF) continue;   // uniform: row i0+t depends on earlier rows
-            const double inv = mod_inv((double)R.brow[t * BMAX + jc], mod);
+            const double inv = inv_fermat((double)R.brow[t * BMAX + jc], mod);
             if (tid == 0) {
                 rpm[i0 + t] = jc;
                 dead[jc] = 1;
@@ -462,7 +536,7 @@ __device__ int zorder(int m, int n, const int32_t *rpm, ZMem &z, int32_t *wcnt) 
 // ------------------------------------------------------------- kernel ----
 
 template <typename T, int KB>
-__global__ __launch_bounds__(BT) void batched_pluq_kernel(const BatchDesc *desc, int32_t batch, char *wbase,
+__global__ __launch_bounds__(BT, KB == 8 ? 4 : 1) void batched_pluq_kernel(const BatchDesc *desc, int32_t batch, char *wbase,
                                                          ModP mod) {
     __shared__ BigMem<KB> big;
     __shared__ int32_t rpm[BMAX];
@@ -476,14 +550,14 @@ __global__ __launch_bounds__(BT) void batched_pluq_kernel(const BatchDesc *desc,
         T *W = (T *)(wbase + d.woff);
         int r = 0;
         if (m > 0 && n > 0) {
-            for (int e = tid; e < m * n; e += BT) W[e] = A[(int64_t)(e / n) * d.lda + e % n];
+            copy_block(A, d.lda, W, (int64_t)n, m, n);
             __syncthreads();
             r = blocked_lu<T, KB>(A, d.lda, m, n, -1, mod, big.lu);
             if (r >= 0) {
                 for (int i = tid; i < m; i += BT) d.P[i] = i;
                 for (int j = tid; j < n; j += BT) d.Q[j] = j;
             } else {
-                for (int e = tid; e < m * n; e += BT) A[(int64_t)(e / n) * d.lda + e % n] = W[e];
+                copy_block((const T *)W, (int64_t)n, A, d.lda, m, n);
                 __syncthreads();
                 const int r1 = rpm_search<T, KB>(A, d.lda, m, n, mod, big.rpm, rpm, dead, sred);
                 const int rz = zorder(m, n, rpm, big.z, sred);
