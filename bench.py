@@ -12,7 +12,13 @@ rate (2 * sum_{k<r} (m-k-1)(n-k-1) per matrix), the roofline position of the
 dominant kernel (the MM update, timed with HIP events on the library's
 stream inside the timed region), and the CPU oracle on a bounded sample.
 
+After the timed region (and not part of `value`): the INT8-limb form on the
+same pair, the 16384 x 16384 rank-12000 workload over GF(65521) and GF(251)
+in every form, and the batch of 4096 small matrices in one persistent launch
+against per-matrix launches (`comparisons`).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-comparisons]
 """
 from __future__ import annotations
 
@@ -89,6 +95,104 @@ def cpu_baseline(seed: int):
                       f"rank-2048 permuted X.Y, {dt:.1f} s"}
 
 
+def _time_decomp(pl, A, p, form, reps=2):
+    """Best-of-reps wall time of one in-place decomposition (input restored
+    from A before each run, outside the timing); returns (rank, seconds)."""
+    import torch
+    X = A.clone()
+    P = torch.empty(A.shape[0], dtype=torch.int64, device=A.device)
+    Q = torch.empty(A.shape[1], dtype=torch.int64, device=A.device)
+    o = pl._opts(form)
+    r = pl.pluq_modp(X, p, P, Q, o)   # warm-up
+    best = float("inf")
+    for _ in range(reps):
+        X.copy_(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = pl.pluq_modp(X, p, P, Q, o)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return r, best
+
+
+def comparisons(pl, c2_pristine, seed):
+    """The other forms and workloads, measured after the timed region: the
+    INT8-limb form on the same 4096 pair; the 16384 x 16384 rank-12000
+    permuted X.Y over GF(65521) and GF(251) in every form; the batch of 4096
+    matrices (m, n ~ U{32..512}, r ~ U{0..min}) in one persistent launch
+    against per-matrix plain launches."""
+    import numpy as np
+    import torch
+    import pluq_inputs as gen
+    out = {}
+    # INT8 form on the benchmark pair
+    secs, ops = 0.0, 0.0
+    for A in c2_pristine:
+        r, t = _time_decomp(pl, A, 65521, "int8")
+        secs += t
+        ops += 2.0 * A.shape[0] * A.shape[1] * r
+    out["c2_4096_pair_int8"] = {"ms_per_step": secs * 1e3, "gops": ops / secs / 1e9}
+    # 16384^2 rank 12000, every form; MM-kernel rate of the INT8 form
+    for p, forms in [(65521, ["fp64", "int8"]), (251, ["fp64", "int8", "fp32"])]:
+        A = gen.xy_permuted(16384, 16384, 12000, p, seed, device="cuda").to(torch.float64)
+        rec = {}
+        for f in forms:
+            r, t = _time_decomp(pl, A, p, f)
+            rec[f] = {"ms": t * 1e3, "gops": 2.0 * 16384 * 16384 * r / t / 1e9, "rank": r}
+        # one more INT8 run with the MM launches timed
+        X = A.clone()
+        P = torch.empty(16384, dtype=torch.int64, device="cuda")
+        Q = torch.empty(16384, dtype=torch.int64, device="cuda")
+        pl.pluq_profile_enable((1 << 0) | (1 << 5))
+        pl.pluq_modp(X, p, P, Q, pl._opts("int8"))
+        prof = pl.pluq_profile_read()
+        pl.pluq_profile_enable(0)
+        mm, lb = prof["modmm"], prof["limb"]
+        nl = 1 if p <= 256 else 2
+        rec["int8_mm_kernels"] = {
+            "mm_launches": mm["launches"], "mm_ms": mm["ms"], "split_ms": lb["ms"],
+            "tflops_2mnk": mm["flops"] / (mm["ms"] * 1e-3) / 1e12 if mm["ms"] else 0.0,
+            "note": f"MM launches of one INT8-form decomposition (large updates on int8 matrix cores, "
+                    f"{nl * nl} limb products per multiply-add; small ones in the FP64 kernel)"}
+        rec["speedup_int8_vs_fp64"] = rec["fp64"]["ms"] / rec["int8"]["ms"]
+        out[f"c4_16384_r12000_p{p}"] = rec
+        del A, X
+        torch.cuda.empty_cache()
+    # batched form: 4096 matrices, int32 storage, GF(65521)
+    p = 65521
+    m, n, r = gen.batch_shapes(4096, seed)
+    pristine = [gen.xy_permuted(int(m[i]), int(n[i]), int(r[i]), p, seed * 1_000_003 + i, device="cuda")
+                .to(torch.int32).contiguous() for i in range(4096)]
+    dev = [t.clone() for t in pristine]
+    Ps = [torch.empty(t.shape[0], dtype=torch.int64, device="cuda") for t in pristine]
+    Qs = [torch.empty(t.shape[1], dtype=torch.int64, device="cuda") for t in pristine]
+    d_r = torch.empty(4096, dtype=torch.int64, device="cuda")
+    call = pl.BatchedCall(dev, p, Ps, Qs, d_r).prepare()
+    best = float("inf")
+    for _ in range(3):
+        for t, s0 in zip(dev, pristine):
+            t.copy_(s0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        call.run()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    ranks = d_r.cpu().numpy()
+    ops = float(np.sum(2.0 * m * n * ranks))
+    for t, s0 in zip(dev, pristine):
+        t.copy_(s0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(4096):
+        pl.pluq_modp(dev[i], p, Ps[i], Qs[i])
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    out["c5_batch4096"] = {"batched_ms": best * 1e3, "batched_gops": ops / best / 1e9,
+                           "per_matrix_plain_ms": plain * 1e3, "per_matrix_plain_gops": ops / plain / 1e9,
+                           "speedup_batched_vs_plain": plain / best, "failed_self_checks": int(np.sum(ranks < 0))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +201,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the other forms and workloads measured after the timed region")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -169,6 +275,8 @@ def main():
                      "traffic": traffic},
         "library_stats_last_call": stats,
     }
+    if not args.no_comparisons:
+        out["comparisons"] = comparisons(pl, pristine, args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.seed)
     print(json.dumps(out), flush=True)
