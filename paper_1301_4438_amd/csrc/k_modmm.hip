@@ -18,8 +18,9 @@
 // v_mfma_f64_16x16x4_f64.  Panels of depth BK are staged in LDS (A row-major,
 // B row-major, both padded); global loads are lane-contiguous row segments;
 // the next panel is fetched into registers while the current one is used.
-// A 64 x 64 tile uses BK = 64, so an update with K <= 64 (the leaves of the
-// triangular solves and the deep Schur updates) needs a single load phase.
+// 64 x 64 and 32 x 32 tiles use BK = 64, so an update with K <= 64 (the
+// leaves of the triangular solves and the deep Schur updates) needs a single
+// load phase.
 //
 // The same kernel in float32 (CT = float, v_mfma_f32_16x16x4_f32) is the
 // FP32 form for small moduli: a float32 sum of integers is exact while it
@@ -207,30 +208,36 @@ static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
 }
 
 template <typename T, typename CT>
-static hipError_t launch_dt(MMArgs &args, int big, int total, hipStream_t st) {
-    return big == 128 ? launch_t<T, CT, 128, 128, 32>(args, total, st) : launch_t<T, CT, 64, 64, 64>(args, total, st);
+static hipError_t launch_dt(MMArgs &args, int tile, int total, hipStream_t st) {
+    switch (tile) {
+    case 128: return launch_t<T, CT, 128, 128, 32>(args, total, st);
+    case 64: return launch_t<T, CT, 64, 64, 64>(args, total, st);
+    default: return launch_t<T, CT, 32, 32, 64>(args, total, st);
+    }
 }
 
 template <typename CT>
 static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
     MMArgs args;
     int n = 0;
-    int64_t tiles128 = 0;
+    int64_t tiles128 = 0, tiles64 = 0;
     for (int q = 0; q < nprob; ++q) {
         if (probs[q].M <= 0 || probs[q].N <= 0) continue;
         args.prob[n++] = probs[q];
         tiles128 += cdiv64(probs[q].M, 128) * cdiv64(probs[q].N, 128);
+        tiles64 += cdiv64(probs[q].M, 64) * cdiv64(probs[q].N, 64);
     }
     if (n == 0) return hipSuccess;
-    // Large updates use 128 x 128 tiles; smaller ones 64 x 64 to keep the
-    // 256 compute units busy.
-    const int big = tiles128 >= 240 ? 128 : 64;
+    // Large updates use 128 x 128 tiles; smaller ones 64 x 64, and the small
+    // updates of the deep recursion (fewer 64-tiles than compute units) 32 x
+    // 32, so that more compute units share their matrix-core work.
+    const int tile = tiles128 >= 240 ? 128 : (tiles64 >= 192 ? 64 : 32);
     int total = 0;
     for (int q = 0; q < n; ++q) {
         MMProblem &pb = args.prob[q];
         pb.tileStart = total;
-        pb.tilesN = (int)cdiv64(pb.N, big);
-        total += (int)(cdiv64(pb.M, big) * pb.tilesN);
+        pb.tilesN = (int)cdiv64(pb.N, tile);
+        total += (int)(cdiv64(pb.M, tile) * pb.tilesN);
         if (pb.K[0] <= 0) pb.K[0] = 0;
         if (pb.K[1] <= 0) pb.K[1] = 0;
     }
@@ -240,9 +247,9 @@ static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p,
     args.mod.pinv = 1.0 / p;
     args.mod.half = (double)((int64_t)p / 2);
     switch (dtype) {
-    case DT_I64: return launch_dt<int64_t, CT>(args, big, total, st);
-    case DT_F64: return launch_dt<double, CT>(args, big, total, st);
-    case DT_I32: return launch_dt<int32_t, CT>(args, big, total, st);
+    case DT_I64: return launch_dt<int64_t, CT>(args, tile, total, st);
+    case DT_F64: return launch_dt<double, CT>(args, tile, total, st);
+    case DT_I32: return launch_dt<int32_t, CT>(args, tile, total, st);
     }
     return hipErrorInvalidValue;
 }
