@@ -60,6 +60,21 @@ __device__ __forceinline__ double mod_inv(double a_, const ModP &m) {
     return (double)t;
 }
 
+// Inverse of a non-zero canonical residue by Fermat's little theorem,
+// a^(p-2) mod p, square-and-multiply on exact float64 products: a fixed,
+// wave-uniform sequence of about 2 log2(p) modular products, shorter in
+// latency than the Euclidean algorithm's chain of integer divisions.
+__device__ __forceinline__ double inv_fermat(double a, const ModP &mod) {
+    uint32_t e = (uint32_t)mod.p - 2u;
+    double r = 1.0, b = a;
+    while (e) {
+        if (e & 1u) r = mod_reduce(r * b, mod);
+        b = mod_reduce(b * b, mod);
+        e >>= 1;
+    }
+    return r;
+}
+
 __host__ __device__ inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace pluq

@@ -315,6 +315,7 @@ void Ctx::trsm_llu_rec(const char *L, int64_t ldl, int64_t r, char *B, int64_t l
     if (r <= TRSM_NB) {
         MMProblem pb = mmprob(B, ldb, r, ncols);
         mmpair(pb, 0, trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz, TRSM_NB, B, ldb, r);
+        pb.inplace = 1;   // C is the B operand
         mm(&pb, 1);
         return;
     }
@@ -339,6 +340,7 @@ void Ctx::trsm_run_rec(char *B, int64_t ldb, int64_t nrows, const char *U, int64
     if (r <= TRSM_NB) {
         MMProblem pb = mmprob(B, ldb, nrows, r);
         mmpair(pb, 0, B, ldb, trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz, TRSM_NB, r);
+        pb.inplace = 2;   // C is the A operand
         mm(&pb, 1);
         return;
     }
@@ -460,6 +462,9 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     launch(K_BASE, 0, tbytes, [&] {
         return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table, d_stat + STAT_BC, st);
     });
+    // self-check of the ordered elimination: r non-zero pivots, zero remainder
+    read_status(STAT_BC, 2);
+    if (h_stat[STAT_BC + 1] != 1 || h_stat[STAT_BC] != r) throw DeviceError{hipErrorUnknown};
     return r;
 }
 

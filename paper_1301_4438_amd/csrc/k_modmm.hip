@@ -208,12 +208,12 @@ static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
 }
 
 template <typename T, typename CT>
-static hipError_t launch_dt(MMArgs &args, int tile, int total, hipStream_t st) {
-    switch (tile) {
-    case 128: return launch_t<T, CT, 128, 128, 32>(args, total, st);
-    case 64: return launch_t<T, CT, 64, 64, 64>(args, total, st);
-    default: return launch_t<T, CT, 32, 32, 64>(args, total, st);
-    }
+static hipError_t launch_dt(MMArgs &args, int bm, int bn, int total, hipStream_t st) {
+    if (bm == 128) return launch_t<T, CT, 128, 128, 32>(args, total, st);
+    if (bm == 64 && bn == 64) return launch_t<T, CT, 64, 64, 64>(args, total, st);
+    if (bm == 64) return launch_t<T, CT, 64, 32, 64>(args, total, st);
+    if (bn == 64) return launch_t<T, CT, 32, 64, 64>(args, total, st);
+    return launch_t<T, CT, 32, 32, 64>(args, total, st);
 }
 
 template <typename CT>
@@ -221,23 +221,35 @@ static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p,
     MMArgs args;
     int n = 0;
     int64_t tiles128 = 0, tiles64 = 0;
+    int inplace = 0;   // bit 0: some C is its B operand, bit 1: some C is its A operand
     for (int q = 0; q < nprob; ++q) {
         if (probs[q].M <= 0 || probs[q].N <= 0) continue;
+        if ((probs[q].inplace == 1 && probs[q].M > 64) || (probs[q].inplace == 2 && probs[q].N > 64) ||
+            probs[q].inplace < 0 || probs[q].inplace > 2)
+            return hipErrorInvalidValue;
         args.prob[n++] = probs[q];
         tiles128 += cdiv64(probs[q].M, 128) * cdiv64(probs[q].N, 128);
         tiles64 += cdiv64(probs[q].M, 64) * cdiv64(probs[q].N, 64);
+        if (probs[q].inplace) inplace |= 1 << (probs[q].inplace - 1);
     }
     if (n == 0) return hipSuccess;
     // Large updates use 128 x 128 tiles; smaller ones 64 x 64, and the small
     // updates of the deep recursion (fewer 64-tiles than compute units) 32 x
-    // 32, so that more compute units share their matrix-core work.
-    const int tile = tiles128 >= 240 ? 128 : (tiles64 >= 192 ? 64 : 32);
+    // 32, so that more compute units share their matrix-core work.  An
+    // in-place update keeps 64 along the dimension it shares with C.
+    int bm, bn;
+    if (tiles128 >= 240) bm = bn = 128;
+    else if (tiles64 >= 192 || inplace == 3) bm = bn = 64;
+    else {
+        bm = (inplace & 1) ? 64 : 32;
+        bn = (inplace & 2) ? 64 : 32;
+    }
     int total = 0;
     for (int q = 0; q < n; ++q) {
         MMProblem &pb = args.prob[q];
         pb.tileStart = total;
-        pb.tilesN = (int)cdiv64(pb.N, tile);
-        total += (int)(cdiv64(pb.M, tile) * pb.tilesN);
+        pb.tilesN = (int)cdiv64(pb.N, bn);
+        total += (int)(cdiv64(pb.M, bm) * pb.tilesN);
         if (pb.K[0] <= 0) pb.K[0] = 0;
         if (pb.K[1] <= 0) pb.K[1] = 0;
     }
@@ -247,9 +259,9 @@ static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p,
     args.mod.pinv = 1.0 / p;
     args.mod.half = (double)((int64_t)p / 2);
     switch (dtype) {
-    case DT_I64: return launch_dt<int64_t, CT>(args, tile, total, st);
-    case DT_F64: return launch_dt<double, CT>(args, tile, total, st);
-    case DT_I32: return launch_dt<int32_t, CT>(args, tile, total, st);
+    case DT_I64: return launch_dt<int64_t, CT>(args, bm, bn, total, st);
+    case DT_F64: return launch_dt<double, CT>(args, bm, bn, total, st);
+    case DT_I32: return launch_dt<int32_t, CT>(args, bm, bn, total, st);
     }
     return hipErrorInvalidValue;
 }

@@ -21,6 +21,10 @@ struct MMProblem {
     int32_t M, N;
     int32_t *nzflag;   // if non-null: set to nzgen when an output element is non-zero
     int32_t nzgen;
+    int32_t inplace;   // C is also an operand (a triangular-solve leaf):
+                       // 1 = C is the B operand (M <= 64), 2 = C is the A
+                       // operand (N <= 64).  The tile then spans all of M
+                       // (or N), so no work-group writes what another reads.
     int32_t tileStart; // filled by the launcher
     int32_t tilesN;    // filled by the launcher
 };
@@ -75,15 +79,6 @@ struct BatchDesc {
 // kb: panel width (8 or 16); grid: persistent work-groups.
 hipError_t launch_batched_pluq(int dtype, int kb, const BatchDesc *desc, int32_t batch, char *wbase,
                                double p, int grid, hipStream_t st);
-
-// Left lower unit TRSM leaf: B (nb x ncols, ldb) <- L^{-1} B, nb <= 64.
-hipError_t launch_trsm_llu_leaf(int dtype, const void *L, int64_t ldl, int nb, void *B,
-                                int64_t ldb, int64_t ncols, double p, int kchunk,
-                                hipStream_t st);
-// Right upper non-unit TRSM leaf: B (nrows x nb, ldb) <- B U^{-1}, nb <= 64.
-hipError_t launch_trsm_run_leaf(int dtype, void *B, int64_t ldb, int64_t nrows,
-                                const void *U, int64_t ldu, int nb, double p, int kchunk,
-                                hipStream_t st);
 
 // Inverses of the 64 x 64 diagonal blocks of an r x r triangle (side 0:
 // unit lower, side 1: upper non-unit), written as I - T_qq^{-1} (canonical,
