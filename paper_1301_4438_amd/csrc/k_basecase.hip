@@ -25,9 +25,8 @@
 // (ty + 16a, tx + 16b), R = TILE / 16, in registers, so the shrinking trailing
 // block stays evenly spread over the threads.  Register indices that depend
 // on the step are resolved by a wave-uniform switch, never by indexing.
-// Pivot inverses come from an LDS table of inverses when p <= 65536 (then
-// tiles are at most 64 x 64 so that table and output tile share the LDS),
-// else from the extended Euclidean algorithm.
+// Pivot inverses come from an LDS table of inverses when p <= 65536, else
+// from the extended Euclidean algorithm.
 // Arithmetic uses delayed reduction (Section 6) inside the elimination: the
 // update is one FMA of symmetric residues on an exact integer-valued double,
 // an entry is reduced when it joins a pivot row or column, and every entry is
@@ -50,21 +49,25 @@ __global__ __launch_bounds__(256) void build_inv_table_kernel(uint16_t *tab, Mod
 }
 
 // bc_lu step structure (one step = one pivot s):
-//   P1  every thread finalises one entry of the pivot row or column:
-//       reads its raw value from LDS, reduces it, writes the final U (row) or
-//       L (column) value to the LDS output tile and publishes the symmetric
+//   P1  every thread finalises one entry of the pivot row or column: reads
+//       its raw value from LDS, reduces it and publishes the symmetric
 //       residue used by the update (the multipliers are the column scaled by
 //       the pivot's inverse, which each thread looks up itself);
 //   P2  every thread applies the rank-one update to its registers with
 //       branch-free FMAs (inactive rows and columns were published as zero),
 //       and the owners of row and column s+1 copy them to LDS for the next P1.
-// Two barriers per step; the output tile is copied to global memory only on
-// success, so a failed optimistic attempt leaves the input untouched.
+// Two barriers per step.  Once a row or column has been a pivot row or
+// column its registers are never changed again (it is published as zero),
+// so the result is read from the registers at the end: U entries reduced,
+// L entries reduced and multiplied by their pivot's inverse (kept in LDS).
+// A is written only on success, so a failed optimistic attempt leaves the
+// input untouched.
 struct BcShared {
     double row[BC_DIM];   // raw entries of the next pivot row
     double col[BC_DIM];   // raw entries of the next pivot column
     double Lb[BC_DIM];    // published multipliers (symmetric)
     double Ub[BC_DIM];    // published pivot row (symmetric)
+    double inv[BC_DIM];   // inverse of each pivot
 };
 
 __device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const uint16_t *tab) {
@@ -72,9 +75,7 @@ __device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const ui
     return tab ? (double)tab[(int)x] : mod_inv(x, mod);
 }
 
-// OUT is the output tile's word type: uint16_t when residues fit (p <= 65536),
-// uint32_t otherwise.
-template <typename T, int TILE, typename OUT>
+template <typename T, int TILE>
 __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, int m, int n,
                                                            const int32_t *rmap, const int32_t *cmap,
                                                            int r_known, ModP mod, int kchunk,
@@ -84,24 +85,13 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
     __shared__ BcShared sh;
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
-    OUT *out = (OUT *)dyn;                                   // TILE x TILE
     const uint16_t *tab = nullptr;
-    constexpr size_t OUT_BYTES = (size_t)TILE * TILE * sizeof(OUT);
 
-    // zero the output tile; copy the inverse table (16-byte words, in flight together)
-    {
-        uint4 *o4 = (uint4 *)dyn;
-        constexpr int OW = (int)(OUT_BYTES / 16);
-#pragma unroll
-        for (int k = 0; k < (OW + BC_THREADS - 1) / BC_THREADS; ++k) {
-            const int w = tid + k * BC_THREADS;
-            if (w < OW) o4[w] = make_uint4(0, 0, 0, 0);
-        }
-    }
+    // copy the inverse table (16-byte words, in flight together)
     if (gtab) {
         const int words = ((int)mod.p + 7) / 8;
         const uint4 *src = (const uint4 *)gtab;
-        uint4 *dst = (uint4 *)(dyn + OUT_BYTES);
+        uint4 *dst = (uint4 *)dyn;
         constexpr int PER = BC_TAB_MAX / 8 / BC_THREADS;   // 16-byte words per thread
         constexpr int CH = 8;                               // loads in flight per thread
 #pragma unroll
@@ -118,7 +108,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
                 if (w < words) dst[w] = tmp[k];
             }
         }
-        tab = (const uint16_t *)(dyn + OUT_BYTES);
+        tab = (const uint16_t *)dyn;
     }
 
     double v[R][R];
@@ -171,14 +161,12 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         if (tid < TILE) {
             const int j = tid;
             const double u = mod_reduce(sh.row[j], mod);
-            const bool act = (j < n);
-            if (act && j >= s) out[s * TILE + j] = (OUT)u;
-            sh.Ub[j] = (act && j > s) ? to_sym(u, mod) : 0.0;
+            sh.Ub[j] = (j > s && j < n) ? to_sym(u, mod) : 0.0;
+            if (j == 0) sh.inv[s] = inv;
         } else if (tid < 2 * TILE) {
             const int i = tid - TILE;
             const bool act = (i > s) && (i < m);
             const double l = mod_mul(mod_reduce(sh.col[i], mod), inv, mod);
-            if (act) out[i * TILE + s] = (OUT)l;
             sh.Lb[i] = act ? to_sym(l, mod) : 0.0;
         }
         __syncthreads();
@@ -227,6 +215,18 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         }
         __syncthreads();
     }
+    if (ok && r_known >= 0 && r < kmax) {
+        // the rank is known: the block left after it must be zero
+        int any = 0;
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) {
+                const int i = ty + 16 * a, j = tx + 16 * b;
+                if (i >= r && j >= r && i < m && j < n) any |= (mod_reduce(v[a][b], mod) != 0.0);
+            }
+        ok = __syncthreads_or(any) == 0;
+    }
     if (!ok) {
         if (tid == 0) { status[0] = r; status[1] = 0; }
         return;
@@ -237,7 +237,11 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
 #pragma unroll
         for (int b = 0; b < R; ++b) {
             const int j = tx + 16 * b;
-            if (i < m && j < n) A[(int64_t)i * lda + j] = from_f64<T>((double)out[i * TILE + j]);
+            if (i < m && j < n) {
+                double x = mod_reduce(v[a][b], mod);
+                if (j < r && i > j) x = mod_mul(x, sh.inv[j], mod);   // L entry
+                A[(int64_t)i * lda + j] = from_f64<T>(x);
+            }
         }
     }
     if (tid == 0) { status[0] = r; status[1] = 1; }
@@ -361,41 +365,32 @@ static bool g_tab_ok = false;
 
 int bc_capacity() { return BC_DIM; }
 
-// LDS of the tile kernels: the output tile (64 x 64 x 2 B with the table of
-// inverses, 128 x 128 x 2 or 4 B without) plus the 128 KB table when used.
-constexpr size_t BC_LDS_TAB = BC_TAB_BYTES + (size_t)64 * 64 * sizeof(uint16_t);
-constexpr size_t BC_LDS_BIG = (size_t)BC_DIM * BC_DIM * sizeof(uint32_t);
-
+// Dynamic LDS of the tile kernel: the 128 KB table of inverses when used.
 hipError_t bc_init() {
     // The LDS inverse table needs a large dynamic LDS allocation; without it
-    // the kernels compute inverses by the extended Euclidean algorithm.
+    // the kernel computes inverses by the extended Euclidean algorithm.
     g_tab_ok = true;
-#define PLUQ_SETLDS(K, BYTES, FLAG)                                                                         \
-    if (hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, (int)(BYTES)) != \
-        hipSuccess)                                                                                         \
-        FLAG = false;
-    bool big_ok = true;
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64, uint16_t>), BC_LDS_TAB, g_tab_ok)
-    PLUQ_SETLDS((bc_lu_kernel<double, 64, uint16_t>), BC_LDS_TAB, g_tab_ok)
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64, uint16_t>), BC_LDS_TAB, g_tab_ok)
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, uint16_t>), BC_LDS_BIG, big_ok)
-    PLUQ_SETLDS((bc_lu_kernel<double, 128, uint16_t>), BC_LDS_BIG, big_ok)
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, uint16_t>), BC_LDS_BIG, big_ok)
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, uint32_t>), BC_LDS_BIG, big_ok)
-    PLUQ_SETLDS((bc_lu_kernel<double, 128, uint32_t>), BC_LDS_BIG, big_ok)
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, uint32_t>), BC_LDS_BIG, big_ok)
+#define PLUQ_SETLDS(K)                                                                                 \
+    if (hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize,               \
+                            (int)BC_TAB_BYTES) != hipSuccess)                                           \
+        g_tab_ok = false;
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64>))
+    PLUQ_SETLDS((bc_lu_kernel<double, 64>))
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64>))
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128>))
+    PLUQ_SETLDS((bc_lu_kernel<double, 128>))
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128>))
 #undef PLUQ_SETLDS
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-        prop.sharedMemPerBlock < BC_LDS_TAB + sizeof(BcShared) + 1024)
+        prop.sharedMemPerBlock < BC_TAB_BYTES + sizeof(BcShared) + 1024)
         g_tab_ok = false;
     (void)hipGetLastError();
-    (void)big_ok;   // 64 KB of dynamic LDS is available on every CDNA part
     return hipSuccess;
 }
 
-int bc_tile_limit(double p) { return (g_tab_ok && p <= BC_TAB_MAX) ? 64 : BC_DIM; }
+int bc_tile_limit(double p) { (void)p; return BC_DIM; }
 
 size_t bc_table_bytes(double p) { return (g_tab_ok && p <= BC_TAB_MAX) ? BC_TAB_BYTES : 0; }
 
@@ -406,23 +401,23 @@ hipError_t launch_build_inv_table(uint16_t *tab, double p, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int TILE, typename OUT>
+template <int TILE>
 static hipError_t bc_lu_t(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
                           const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
                           int32_t *status, hipStream_t st) {
-    const size_t lds = (size_t)TILE * TILE * sizeof(OUT) + (tab ? BC_TAB_BYTES : 0);
+    const size_t lds = tab ? BC_TAB_BYTES : 0;
     const ModP md = make_mod(p);
     switch (dtype) {
     case DT_I64:
-        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE, OUT>), dim3(1), dim3(BC_THREADS), lds, st, (int64_t *)A, lda,
+        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE>), dim3(1), dim3(BC_THREADS), lds, st, (int64_t *)A, lda,
                     m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     case DT_F64:
-        PLUQ_LAUNCH((bc_lu_kernel<double, TILE, OUT>), dim3(1), dim3(BC_THREADS), lds, st, (double *)A, lda,
+        PLUQ_LAUNCH((bc_lu_kernel<double, TILE>), dim3(1), dim3(BC_THREADS), lds, st, (double *)A, lda,
                     m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     case DT_I32:
-        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE, OUT>), dim3(1), dim3(BC_THREADS), lds, st, (int32_t *)A, lda,
+        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE>), dim3(1), dim3(BC_THREADS), lds, st, (int32_t *)A, lda,
                     m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     default: return hipErrorInvalidValue;
@@ -434,15 +429,10 @@ hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int
                         const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
                         int32_t *status, hipStream_t st) {
     if (m > BC_DIM || n > BC_DIM || m <= 0 || n <= 0 || kchunk < 1) return hipErrorInvalidValue;
-    // With the table of inverses only 64 x 64 tiles fit the LDS next to it.
-    // Residues fit 16-bit words exactly when p <= 65536.
-    if (tab) {
-        if (p > BC_TAB_MAX || m > 64 || n > 64) return hipErrorInvalidValue;
-        return bc_lu_t<64, uint16_t>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, st);
-    }
-    if (p <= 65536)
-        return bc_lu_t<128, uint16_t>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, nullptr, status, st);
-    return bc_lu_t<128, uint32_t>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, nullptr, status, st);
+    if (tab && p > BC_TAB_MAX) return hipErrorInvalidValue;
+    if (m <= 64 && n <= 64)
+        return bc_lu_t<64>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, st);
+    return bc_lu_t<128>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, st);
 }
 
 hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,
