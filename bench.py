@@ -34,6 +34,8 @@ if ROOT not in sys.path:
 
 METRIC = "effective GOPS (2mnr) of PLUQ mod p, INT8-limb & batched vs plain FP64"
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP32_MFMA_PEAK_TFLOPS = 157.3
+INT8_MFMA_PEAK_TOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
 
 
@@ -116,6 +118,41 @@ def _time_decomp(pl, A, p, form, reps=2):
     return r, best
 
 
+def large_update(pl, seed):
+    """One large update on its own, 8192 x 8192 x 4096 (one INT8 launch
+    deep), in every form: time per call and the fraction of the form's peak."""
+    import torch
+    mmr = {}
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    for p, form in [(65521, "fp64"), (65521, "int8"), (251, "int8"), (251, "fp32")]:
+        C = torch.randint(0, p, (8192, 8192), device="cuda", generator=g, dtype=torch.int64).to(torch.float64)
+        Aop = torch.randint(0, p, (8192, 4096), device="cuda", generator=g, dtype=torch.int64).to(torch.float64)
+        Bop = torch.randint(0, p, (4096, 8192), device="cuda", generator=g, dtype=torch.int64).to(torch.float64)
+        pl.pluq_modmm(C, Aop, Bop, p, form=form)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            pl.pluq_modmm(C, Aop, Bop, p, form=form)
+        e1.record(); torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        tf = 2.0 * 8192 * 8192 * 4096 / (ms * 1e-3) / 1e12
+        rec = {"ms": ms, "tflops_2mnk": tf}
+        if form == "int8":
+            nl = 1 if p <= 256 else 2
+            rec["int8_tops"] = tf * nl * nl
+            rec["frac_of_int8_peak"] = tf * nl * nl / INT8_MFMA_PEAK_TOPS
+            rec["includes"] = "digit split of both operands and the int8 GEMM"
+        elif form == "fp64":
+            rec["frac_of_fp64_peak"] = tf / FP64_MFMA_PEAK_TFLOPS
+        else:
+            rec["frac_of_fp32_peak"] = tf / FP32_MFMA_PEAK_TFLOPS
+        mmr[f"{form}_p{p}"] = rec
+        del C, Aop, Bop
+    torch.cuda.empty_cache()
+    return mmr
+
+
 def comparisons(pl, c2_pristine, seed):
     """The other forms and workloads, measured after the timed region: the
     INT8-limb form on the same 4096 pair; the 16384 x 16384 rank-12000
@@ -159,6 +196,7 @@ def comparisons(pl, c2_pristine, seed):
         out[f"c4_16384_r12000_p{p}"] = rec
         del A, X
         torch.cuda.empty_cache()
+    out["mm_8192x8192x4096"] = large_update(pl, seed)
     # batched form: 4096 matrices, int32 storage, GF(65521)
     p = 65521
     m, n, r = gen.batch_shapes(4096, seed)
@@ -204,6 +242,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparisons", action="store_true",
                     help="skip the other forms and workloads measured after the timed region")
+    ap.add_argument("--only-mm", action="store_true",
+                    help="time only the 8192 x 8192 x 4096 update in every form (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -212,6 +252,9 @@ def main():
     import torch
     import paper_1301_4438_amd as pl
     pl.load()
+    if args.only_mm:
+        print(json.dumps({"mm_8192x8192x4096": large_update(pl, args.seed)}), flush=True)
+        return
     p, pristine, desc = make_workload(args.workload, args.seed)
     work = [a.clone() for a in pristine]
     Ps = [torch.empty(a.shape[0], dtype=torch.int64, device="cuda") for a in pristine]
@@ -234,7 +277,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         if k == args.steps - 1:
-            pl.pluq_profile_enable(1 << 0)
+            pl.pluq_profile_enable(-1)      # every kernel class, last step only
         ranks = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -274,6 +317,8 @@ def main():
                      "profiled_steps": 1,
                      "algorithmic_bytes_per_launch": mm["bytes"] / max(mm["launches"], 1),
                      "traffic": traffic},
+        "device_ms_per_class_in_profiled_step": {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]},
+        "launches_per_class_in_profiled_step": {c: v["launches"] for c, v in prof.items() if v["launches"]},
         "library_stats_last_call": stats,
     }
     if not args.no_comparisons:
