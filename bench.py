@@ -1,7 +1,8 @@
 """Benchmark of the rank-profile PLUQ on one MI355X.
 
 A step is one whole decomposition of each matrix of the workload (restored
-from a pristine device copy first, since the decomposition is in place).
+from a pristine device copy first, since the decomposition is in place); the
+two decompositions of a step run concurrently on two HIP streams.
 Default workload: 4096 x 4096 over GF(65521), two matrices per step -- a
 full-rank uniform one and a rank-2048 permuted X.Y product -- in the FP64
 matrix-core form with float64 storage.
@@ -27,6 +28,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -260,30 +262,50 @@ def main():
     Ps = [torch.empty(a.shape[0], dtype=torch.int64, device="cuda") for a in pristine]
     Qs = [torch.empty(a.shape[1], dtype=torch.int64, device="cuda") for a in pristine]
     opts = pl._opts("fp64")
+    # The matrices of a step are independent decompositions: each runs on its
+    # own HIP stream from its own host thread (the library keeps its host
+    # state per thread), with its own workspace, so that one decomposition's
+    # latency-bound stretches (base cases, small updates, rank readbacks)
+    # overlap with the other's work.
+    streams = [torch.cuda.Stream() for _ in pristine]
+    wss = [torch.empty(max(pl.pluq_workspace_size(a.shape[0], a.shape[1], 1, p, opts), 256),
+                       dtype=torch.uint8, device="cuda") for a in pristine]
+    pool = ThreadPoolExecutor(max_workers=len(pristine))
 
-    def step():
-        rs = []
-        for i in range(len(work)):
+    def one(i, profile):
+        with torch.cuda.stream(streams[i]):
+            if profile:
+                pl.pluq_profile_enable(-1)   # every kernel class, last step only
             work[i].copy_(pristine[i])
-            rs.append(pl.pluq_modp(work[i], p, Ps[i], Qs[i], opts))
-        return rs
+            r = pl.pluq_modp(work[i], p, Ps[i], Qs[i], opts, wss[i])
+            prof = pl.pluq_profile_read() if profile else None
+            if profile:
+                pl.pluq_profile_enable(0)
+            return r, prof, pl.pluq_last_stats()
+
+    def step(profile=False):
+        return [f.result() for f in [pool.submit(one, i, profile) for i in range(len(work))]]
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # The MM updates of the last timed step are timed per launch with events
+    # The launches of the last timed step are timed one by one with events
     # attached to their dispatches; attaching them costs a few microseconds of
     # launch latency each, so the other steps run without them.
     t0 = time.perf_counter()
     for k in range(args.steps):
-        if k == args.steps - 1:
-            pl.pluq_profile_enable(-1)      # every kernel class, last step only
-        ranks = step()
+        res = step(profile=(k == args.steps - 1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = pl.pluq_profile_read()
-    pl.pluq_profile_enable(0)
-    stats = pl.pluq_last_stats()
+    pool.shutdown()
+    ranks = [r for r, _, _ in res]
+    prof = {}
+    for _, pr, _ in res:
+        for c, v in pr.items():
+            acc = prof.setdefault(c, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+            for key in acc:
+                acc[key] += v[key]
+    stats = res[-1][2]
 
     secs = t1 - t0
     eff_ops = sum(2.0 * a.shape[0] * a.shape[1] * r for a, r in zip(pristine, ranks)) * args.steps
@@ -307,7 +329,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "m": pristine[0].shape[0], "n": pristine[0].shape[1], "p": p,
-                   "ranks": ranks, "form": "fp64", "storage": "float64"},
+                   "ranks": ranks, "form": "fp64", "storage": "float64",
+                   "concurrency": "the two decompositions of a step on two HIP streams"},
         "classical_gops": cls_ops / secs / 1e9,
         "roofline": {"bound": "mfma", "kernel": "modmm_f64", "achieved": achieved,
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",

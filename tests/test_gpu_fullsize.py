@@ -133,3 +133,47 @@ def test_c4_planted_companion(gpu_lib, p):
     assert _order_matches(P, Q, r, n, n)
     assert structure_torch(P, Q, r, X)
     assert freivalds(A, P, Q, r, X, p, trials=2)
+
+
+def test_concurrent_streams_vs_oracle(gpu_lib):
+    """Independent decompositions issued from several host threads, each on
+    its own HIP stream with its own workspace (the way the benchmark runs the
+    two matrices of a step), twice over: each equals the oracle's."""
+    import threading
+    import torch
+    p = 65521
+    mats = [gen.uniform(1024, 1024, p, 11), gen.xy_permuted(1024, 1024, 600, p, 12),
+            gen.zero_block(768, 1280, 500, 128, p, 13), gen.planted_leu(1100, 900, 700, p, 14)[0]]
+    want = [oracle.pluqz(A, p) for A in mats]
+    opts = gpu_lib._opts("fp64")
+    streams = [torch.cuda.Stream() for _ in mats]
+    dev = [torch.from_numpy(np.ascontiguousarray(A)).to(torch.float64).cuda() for A in mats]
+    wss = [torch.empty(gpu_lib.pluq_workspace_size(A.shape[0], A.shape[1], 1, p, opts), dtype=torch.uint8,
+                       device="cuda") for A in mats]
+    for rep in range(2):
+        note("concurrent streams", rep)
+        out = [None] * len(mats)
+        errs = []
+
+        def run(i):
+            try:
+                with torch.cuda.stream(streams[i]):
+                    X = dev[i].clone()
+                    P = torch.empty(X.shape[0], dtype=torch.int64, device="cuda")
+                    Q = torch.empty(X.shape[1], dtype=torch.int64, device="cuda")
+                    r = gpu_lib.pluq_modp(X, p, P, Q, opts, wss[i])
+                    streams[i].synchronize()
+                    out[i] = (P.cpu().numpy(), Q.cpu().numpy(), r, X.cpu().numpy().astype(np.int64))
+            except Exception as e:  # reported on the main thread
+                errs.append((i, e))
+
+        ts = [threading.Thread(target=run, args=(i,)) for i in range(len(mats))]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        assert not errs, errs
+        for i, (Po, Qo, ro, Xo) in enumerate(want):
+            P, Q, r, X = out[i]
+            assert r == ro, i
+            assert np.array_equal(P, Po) and np.array_equal(Q, Qo) and np.array_equal(X, Xo), i
