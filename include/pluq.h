@@ -244,7 +244,9 @@ void pluq_last_stats(int64_t *nodes, int64_t *basecases, int64_t *launches,
  *            outputs read and written once).
  * pluq_profile_enable(mask) resets the counters and records the classes
  * whose bit (1 << class) is set in mask (-1: all, 0: stop); untimed classes
- * cost nothing.  pluq_profile_read fills PLUQ_K_COUNT entries.
+ * cost nothing.  pluq_profile_read fills PLUQ_K_COUNT entries; launches of
+ * the asynchronous entry points (pluq_modmm, pluq_trsm) that are still
+ * pending are waited for first.
  */
 enum {
     PLUQ_K_MODMM = 0,     /* MM updates (Schur complements, TRSM updates) */

@@ -515,6 +515,13 @@ void pluq_profile_enable(int32_t mask) {
 
 void pluq_profile_read(pluq_kernel_stat *out) {
     if (!out) return;
+    // launches of the asynchronous entry points (MM, TRSM) still pending:
+    // wait for their events, which were recorded in issue order
+    if (!g_prof.pending.empty()) {
+        const Profiler::Pending &last = g_prof.pending.back();
+        if (hipEventSynchronize(g_prof.pool[last.e0 + 1]) == hipSuccess) g_prof.resolve();
+        else g_prof.discard();
+    }
     for (int c = 0; c < KCLASSES; ++c) {
         out[c].launches = g_prof.k[c].launches;
         out[c].ms = g_prof.k[c].ms;

@@ -293,8 +293,8 @@ static void mmpair(MMProblem &pb, int s, const void *A, int64_t lda, const void 
 
 // ------------------------------------------------------------------ TRSM --
 
-// Split of a triangle of order r > 64: a multiple of 64 near r/2, so that
-// the leaves are exactly the 64 x 64 diagonal blocks inverted up front.
+// Split of a triangle of order r > 256: a multiple of 64 near r/2, so that
+// every leaf starts on a 64 x 64 diagonal block inverted up front.
 static int64_t trsm_split(int64_t r) {
     const int64_t h = (r / 2) - (r / 2) % TRSM_NB;
     return h < TRSM_NB ? TRSM_NB : h;
@@ -302,8 +302,9 @@ static int64_t trsm_split(int64_t r) {
 
 // TRSM(L, B) of Section 2: B (r x ncols, ldb) <- L^{-1} B, L unit lower r x r.
 // The diagonal blocks are inverted in one launch; the recursion then runs on
-// the matrix cores only: two half solves around an MM update, and at a leaf
-// the in-place product B_q <- B_q - (I - L_qq^{-1}) B_q.
+// the matrix cores only: two half solves around an MM update, down to leaves
+// of order <= 256 solved in one launch each (block forward substitution with
+// the inverted diagonal blocks, one work-group per strip of right-hand sides).
 void Ctx::trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols) {
     if (r <= 0 || ncols <= 0) return;
     launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 2,
@@ -312,11 +313,10 @@ void Ctx::trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb
 }
 
 void Ctx::trsm_llu_rec(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols, int64_t off) {
-    if (r <= TRSM_NB) {
-        MMProblem pb = mmprob(B, ldb, r, ncols);
-        mmpair(pb, 0, trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz, TRSM_NB, B, ldb, r);
-        pb.inplace = 1;   // C is the B operand
-        mm(&pb, 1);
+    if (r <= TRSM_FUSE_MAX) {
+        const char *W = trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
+        launch(K_TRSM, (double)r * r * ncols + 2.0 * TRSM_NB * r * ncols, (0.5 * r * r + 2.0 * r * ncols) * esz,
+               [&] { return launch_trsm_leaf(dt, 0, L, ldl, r, B, ldb, ncols, W, (double)p, kchunk, st); });
         return;
     }
     const int64_t r1 = trsm_split(r);
@@ -328,7 +328,7 @@ void Ctx::trsm_llu_rec(const char *L, int64_t ldl, int64_t r, char *B, int64_t l
 }
 
 // TRSM(B, U) of Section 2: B (nrows x r, ldb) <- B U^{-1}, U upper r x r
-// with non-zero diagonal; same scheme, leaf B_q <- B_q - B_q (I - U_qq^{-1}).
+// with non-zero diagonal; same scheme, the leaf solving the transposed system.
 void Ctx::trsm_run_p(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r) {
     if (r <= 0 || nrows <= 0) return;
     launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 2,
@@ -337,11 +337,10 @@ void Ctx::trsm_run_p(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t
 }
 
 void Ctx::trsm_run_rec(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r, int64_t off) {
-    if (r <= TRSM_NB) {
-        MMProblem pb = mmprob(B, ldb, nrows, r);
-        mmpair(pb, 0, B, ldb, trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz, TRSM_NB, r);
-        pb.inplace = 2;   // C is the A operand
-        mm(&pb, 1);
+    if (r <= TRSM_FUSE_MAX) {
+        const char *W = trsm_w + (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
+        launch(K_TRSM, (double)r * r * nrows + 2.0 * TRSM_NB * r * nrows, (0.5 * r * r + 2.0 * r * nrows) * esz,
+               [&] { return launch_trsm_leaf(dt, 1, U, ldu, r, B, ldb, nrows, W, (double)p, kchunk, st); });
         return;
     }
     const int64_t r1 = trsm_split(r);

@@ -1,11 +1,13 @@
 // Triangular solves of Section 2, TRSM(L, B) and TRSM(B, U): the host driver
 // splits a solve recursively at multiples of 64 into half-size solves and
-// one MM update each; a leaf of order <= 64 is the in-place MM update
-//     B <- B - (I - L_qq^{-1}) B    or    B <- B - B (I - U_qq^{-1}),
-// so every multiply-add of a solve runs in the MM kernel (k_modmm.hip).  This
-// file holds the one kernel the solves need besides MM: the inverses of all
-// 64 x 64 diagonal blocks of the triangle, computed in one launch before the
-// recursion starts.
+// one MM update each (k_modmm.hip).  This file holds the two kernels the
+// solves need besides MM:
+//   * the inverses of all 64 x 64 diagonal blocks of the triangle, computed
+//     in one launch before the recursion starts (stored as I - T_qq^{-1});
+//   * the leaf solve of order r <= 256 in one launch: each work-group owns a
+//     strip of 16 right-hand sides and runs the block forward substitution
+//     X_q = T_qq^{-1} (B_q - sum_{j<q} T_qj X_j) over the 64-row blocks on
+//     the float64 matrix cores, keeping its solved strip in LDS.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -100,6 +102,188 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t
     }
 }
 
+// Leaf solve of order r <= TRSM_FUSE_MAX.  The lower case solves L X = B
+// (L unit lower r x r, B r x nst, right-hand sides = columns); the upper case
+// solves X U = B (B nst x r), i.e. U^T X^T = B^T, so both run as the lower
+// system L' X' = B' with
+//   lower: L'(i, k) = T(i, k),  B'(i, c) = B(i, c),  W'_q(i, k) = W_q(i, k);
+//   upper: L'(i, k) = T(k, i),  B'(i, c) = B(c, i),  W'_q(i, k) = W_q(k, i)
+// (W_q = I - T_qq^{-1} from the diagonal-inverse kernel).  Work-group g owns
+// right-hand sides [16 g, 16 g + 16); wave w owns rows [16 w, 16 w + 16) of
+// each 64-row block and one 16 x 16 matrix-core tile.  For block q:
+//   acc = B'_q - sum_{j<q} L'_qj X_j,    X_q = acc - W'_q acc,
+// written back to B and kept in LDS (symmetric residues) for later blocks.
+// The 64 x 64 operand blocks (L'_qj, then W'_q) form one sequence of jobs:
+// each is read from memory with whole-row loads (coalesced in both
+// orientations), converted once to negated symmetric residues and stored in
+// one of two LDS buffers; the next job's loads are issued before the current
+// job's matrix-core operations, so memory latency hides behind them.  One
+// barrier per job: a buffer is rewritten two jobs after it was read, and
+// every thread has passed the previous job's barrier by then.  Four
+// accumulators take turns, so consecutive matrix-core operations are
+// independent.  Exactness: the accumulators' sum is reduced once per kchunk
+// products, at fixed points (between jobs when kchunk >= 64; after every 16
+// products when RED16, p above about 2^23.5), never behind a run-time test
+// between matrix-core operations.  Rows past r contribute zeros (W' is zero
+// there), right-hand sides past nst are computed on zeros and not stored.
+constexpr int TRSM_STRIP = 16;
+
+template <typename T, bool UPPER, bool RED16>
+__global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt, int r, T *B, int64_t ldb,
+                                                        int nst, const T *W, ModP mod, int kchunk) {
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    __shared__ double Xs[TRSM_FUSE_MAX][TRSM_STRIP + 1];   // solved strip (symmetric)
+    __shared__ double Acc[64][TRSM_STRIP + 1];              // B'_q - sum L' X (symmetric)
+    __shared__ double Ls[2][64][65];                        // operand blocks (negated symmetric)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int c0 = blockIdx.x * TRSM_STRIP;
+    const int col = lane & 15;                 // right-hand side within the strip
+    const int kl = lane >> 4;                  // k offset of this lane's operand
+    const int nb = (r + 63) / 64;
+    const bool cval = c0 + col < nst;
+    const int ccl = cval ? c0 + col : nst - 1; // clamped right-hand side (loads stay in range)
+
+    // Job (q, j), j <= q: j < q is L'_qj, j == q is W'_q.  Thread tid moves
+    // elements e = tid + 256 m, m < 16, of the 64 x 64 block: memory row
+    // e / 64, memory column e % 64 (a whole 512-byte row per wave and load).
+    // Job (q, j), j <= q: j < q is L'_qj, j == q is W'_q.  Thread tid moves
+    // elements e = tid + 256 m, m < 16, of the 64 x 64 block: memory row
+    // tid / 64 + 4 m, memory column tid % 64 (a whole 512-byte row per wave
+    // and load); consecutive m are 4 memory rows apart.
+    const int mr0 = tid >> 6, mc = tid & 63;
+    auto load_job = [&](int q, int j, T *dst) {
+        if (j == q) {
+            const T *src = W + (int64_t)q * 4096 + tid;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) dst[m] = src[256 * m];
+        } else if (UPPER) {
+            // T(64 j + mr, min(64 q + mc, r - 1)) = L'(64 q + mc, 64 j + mr)
+            const int64_t step = 4 * ldt;
+            const T *src = Tm + (int64_t)(64 * j + mr0) * ldt + min(64 * q + mc, r - 1);
+#pragma unroll
+            for (int m = 0; m < 16; ++m) dst[m] = src[m * step];
+        } else {
+            // L'(min(64 q + mr, r - 1), 64 j + mc): rows past r re-read row r - 1
+            const int64_t step = 4 * ldt;
+            const T *src = Tm + (int64_t)(64 * q + mr0) * ldt + 64 * j + mc;
+            const T *last = Tm + (int64_t)(r - 1) * ldt + 64 * j + mc;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const T *ptr = (64 * q + mr0 + 4 * m < r) ? src + m * step : last;   // select the address
+                dst[m] = *ptr;
+            }
+        }
+    };
+    auto store_job = [&](int q, int j, int buf, const T *pre) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int mr = mr0 + 4 * m;
+            // operand entry (i, k) within the block; rows past r are zero
+            const int i = UPPER ? mc : mr, k = UPPER ? mr : mc;
+            const bool ok = (j == q) || (64 * q + i < r);
+            Ls[buf][i][k] = ok ? -to_sym(to_f64(pre[m]), mod) : 0.0;
+        }
+    };
+    auto reduce4 = [&](v4d *x) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            x[0][v] = mod_reduce((x[0][v] + x[1][v]) + (x[2][v] + x[3][v]), mod);
+            x[1][v] = 0.0;
+            x[2][v] = 0.0;
+            x[3][v] = 0.0;
+        }
+    };
+    // one 64-deep product: A operand from Ls[buf], B operand from rows
+    // [kb, kb + 64) of the LDS array bs
+    auto mfma_job = [&](int buf, const double (*bs)[TRSM_STRIP + 1], int kb, v4d *x) {
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const double av = Ls[buf][16 * wv + col][4 * ks + kl];
+            const double bv = bs[kb + 4 * ks + kl][col];
+            x[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x[ks & 3], 0, 0, 0);
+            if (RED16 && (ks & 3) == 3) reduce4(x);
+        }
+    };
+
+    T bq[4];
+    auto load_b = [&](int q) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 64 * q + 16 * wv + kl + 4 * v, ic = i < r ? i : r - 1;
+            bq[v] = UPPER ? B[(int64_t)ccl * ldb + ic] : B[(int64_t)ic * ldb + ccl];
+        }
+    };
+    // Jobs run as one flat sequence (q, j) = (0, 0), (1, 0), (1, 1), (2, 0),
+    // ...; two register sets alternate (the loop is unrolled by two), so the
+    // loads of job n + 1 are issued before job n is stored and have a whole
+    // job's time to arrive.
+    T ra[16], rb[16];
+    v4d x[4];
+    int buf = 0, kacc = 0;
+    auto do_job = [&](int q, int j, T (&cur)[16], T (&nxt)[16]) {
+        const int i0 = 64 * q;
+        if (j == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * wv + kl + 4 * v;
+                x[0][v] = (i < r && cval) ? to_f64(bq[v]) : 0.0;
+                x[1][v] = 0.0;
+                x[2][v] = 0.0;
+                x[3][v] = 0.0;
+            }
+            if (q + 1 < nb) load_b(q + 1);
+            kacc = 0;
+        }
+        if (j < q) load_job(q, j + 1, nxt);
+        else if (q + 1 < nb) load_job(q + 1, 0, nxt);
+        store_job(q, j, buf, cur);
+        if (j == q) {
+            // acc = B'_q - sum L' X, reduced: the W job's right operand
+            reduce4(x);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double sv = to_sym(x[0][v], mod);
+                x[0][v] = sv;
+                Acc[16 * wv + kl + 4 * v][col] = sv;
+            }
+            kacc = 0;
+        }
+        __syncthreads();
+        if (!RED16 && kacc + 64 > kchunk) { reduce4(x); kacc = 0; }
+        if (j < q) mfma_job(buf, Xs, 64 * j, x);
+        else mfma_job(buf, Acc, 0, x);
+        kacc += 64;
+        buf ^= 1;
+        if (j == q) {
+            reduce4(x);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * wv + kl + 4 * v;   // < 64 nb <= TRSM_FUSE_MAX
+                const double y = x[0][v];
+                Xs[i][col] = (i < r) ? to_sym(y, mod) : 0.0;
+                if (i < r && cval) {
+                    if (UPPER) B[(int64_t)(c0 + col) * ldb + i] = from_f64<T>(y);
+                    else B[(int64_t)i * ldb + c0 + col] = from_f64<T>(y);
+                }
+            }
+        }
+    };
+    load_b(0);
+    load_job(0, 0, ra);
+    int q = 0, j = 0;
+    auto advance = [&]() {
+        if (j < q) ++j;
+        else { ++q; j = 0; }
+    };
+    while (q < nb) {
+        do_job(q, j, ra, rb);
+        advance();
+        if (q >= nb) break;
+        do_job(q, j, rb, ra);
+        advance();
+    }
+}
+
 static ModP make_mod(double p) {
     ModP m;
     m.p = p;
@@ -127,6 +311,36 @@ hipError_t launch_trsm_diag_inv(int dtype, int side, const void *Tm, int64_t ldt
     case DT_I64: return diag_inv_t<int64_t>(side, Tm, ldt, (int)r, W, p, st);
     case DT_F64: return diag_inv_t<double>(side, Tm, ldt, (int)r, W, p, st);
     case DT_I32: return diag_inv_t<int32_t>(side, Tm, ldt, (int)r, W, p, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t leaf_t(int side, const void *Tm, int64_t ldt, int r, void *B, int64_t ldb, int nst,
+                         const void *W, double p, int kchunk, hipStream_t st) {
+    const dim3 grid((unsigned)cdiv64(nst, TRSM_STRIP));
+    const ModP md = make_mod(p);
+#define PLUQ_LEAF(U, R16)                                                                              \
+    PLUQ_LAUNCH((trsm_leaf_kernel<T, U, R16>), grid, dim3(256), 0, st, (const T *)Tm, ldt, r, (T *)B, ldb, nst, \
+                (const T *)W, md, kchunk)
+    const bool r16 = kchunk < 64;
+    if (side == 0) {
+        if (r16) PLUQ_LEAF(false, true); else PLUQ_LEAF(false, false);
+    } else {
+        if (r16) PLUQ_LEAF(true, true); else PLUQ_LEAF(true, false);
+    }
+#undef PLUQ_LEAF
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_leaf(int dtype, int side, const void *Tm, int64_t ldt, int64_t r, void *B, int64_t ldb,
+                            int64_t nst, const void *W, double p, int kchunk, hipStream_t st) {
+    if (r <= 0 || nst <= 0) return hipSuccess;
+    if (r > TRSM_FUSE_MAX || kchunk < 16 || nst > INT32_MAX) return hipErrorInvalidValue;
+    switch (dtype) {
+    case DT_I64: return leaf_t<int64_t>(side, Tm, ldt, (int)r, B, ldb, (int)nst, W, p, kchunk, st);
+    case DT_F64: return leaf_t<double>(side, Tm, ldt, (int)r, B, ldb, (int)nst, W, p, kchunk, st);
+    case DT_I32: return leaf_t<int32_t>(side, Tm, ldt, (int)r, B, ldb, (int)nst, W, p, kchunk, st);
     }
     return hipErrorInvalidValue;
 }

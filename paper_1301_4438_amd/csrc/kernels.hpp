@@ -87,6 +87,15 @@ constexpr int TRSM_NB = 64;
 hipError_t launch_trsm_diag_inv(int dtype, int side, const void *T, int64_t ldt, int64_t r, void *W,
                                 double p, int kchunk, hipStream_t st);
 
+// Leaf solve of order r <= TRSM_FUSE_MAX in one launch, with the diagonal
+// blocks' W = I - T_qq^{-1} from launch_trsm_diag_inv (W points at block 0
+// of this triangle).  side 0: B (r x nst, ldb) <- L^{-1} B, L unit lower;
+// side 1: B (nst x r, ldb) <- B U^{-1}, U upper.  kchunk: products summed
+// between reductions (at least 16).
+constexpr int TRSM_FUSE_MAX = 256;
+hipError_t launch_trsm_leaf(int dtype, int side, const void *T, int64_t ldt, int64_t r, void *B, int64_t ldb,
+                            int64_t nst, const void *W, double p, int kchunk, hipStream_t st);
+
 // dst[i][j] = src[rmap ? rmap[i] : i][cmap ? cmap[j] : j], rows x cols.
 hipError_t launch_gather2d(int dtype, const void *src, int64_t lds, void *dst, int64_t ldd,
                            int64_t rows, int64_t cols, const int32_t *rmap,

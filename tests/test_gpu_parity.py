@@ -76,11 +76,15 @@ def test_modmm_strided_views(gpu_lib):
 # -------------------------------------------------------------- TRSM --------
 
 @pytest.mark.parametrize("dtype", ["int64", "float64"])
-@pytest.mark.parametrize("p", [3, 65521, 8388593])
+@pytest.mark.parametrize("p", [3, 65521, 8388593, 33554393])
 def test_trsm_parity(gpu_lib, dtype, p):
+    """Orders below, at and above the one-launch leaf limit (256) with ragged
+    64-row blocks and ragged strips of right-hand sides; p = 33554393 makes
+    the leaf reduce its accumulator every 16 products."""
     import torch
     g = np.random.default_rng(7 * p)
-    for r, other in [(1, 1), (5, 300), (64, 64), (65, 257), (130, 90), (200, 1000)]:
+    for r, other in [(1, 1), (5, 300), (64, 64), (65, 257), (130, 90), (200, 1000), (256, 17), (257, 40),
+                     (300, 77), (520, 130)]:
         note("trsm", dtype, p, r, other)
         L = np.tril(g.integers(0, p, (r, r)), -1) + np.triu(g.integers(0, p, (r, r)))  # diag/upper ignored
         B = g.integers(0, p, (r, other))
