@@ -122,6 +122,12 @@ size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p,
  *   opts     NULL for defaults (FP64 form, no validation).
  *   dWork    device workspace of work_bytes >= pluq_workspace_size(...),
  *            256-byte aligned; its contents are scratch.
+ *   stream   HIP stream the work is ordered on (NULL: the null stream).  The
+ *            call returns when the decomposition is complete.  Part of the
+ *            work (the two independent triangular solves of each recursion
+ *            node) runs on an auxiliary stream of the calling thread, forked
+ *            from and joined back into `stream` with events; that stream is
+ *            created on the first call of each thread and device.
  * m == 0 or n == 0 gives r = 0 and identity permutations.
  * Errors: PLUQ_ERR_ARG, PLUQ_ERR_MODULUS, PLUQ_ERR_UNSUPPORTED,
  * PLUQ_ERR_WORKSPACE (all before A is touched), PLUQ_ERR_RANGE (validation

@@ -2,7 +2,7 @@
 //
 // node() follows the algorithm's block steps on the device-resident matrix:
 //   PLUQ(A1); PermR(A2, P1^T); PermC(A3, Q1^T);
-//   D <- L1^{-1} B1; E <- C1 U1^{-1};
+//   D <- L1^{-1} B1; E <- C1 U1^{-1}  (concurrently, on two streams);
 //   F <- B2 - M1 D; G <- C2 - E V1; H <- A4 - E D        (one grouped MM launch)
 //   PLUQ(F); PLUQ(G);
 //   H <- P3^T H Q2^T; E <- P3^T E; M1 <- P2^T M1; D <- D Q2^T; V1 <- V1 Q3^T;
@@ -524,8 +524,21 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
     Zero zFGH[3] = {Z_UNKNOWN, Z_UNKNOWN, Z_UNKNOWN};
     int32_t gFGH[3] = {0, 0, 0};
     if (r1 > 0) {
+        // D <- L1^{-1} B1 and E <- C1 U1^{-1} read and write disjoint blocks:
+        // E is solved on the auxiliary stream while D is solved here
+        const bool fork = aux && n - h > 0 && m - k > 0;
+        if (fork) {
+            check(hipEventRecord(ev_fork, st));
+            check(hipStreamWaitEvent(aux, ev_fork, 0));
+            on_aux([&] { trsm_run(gi + k, gj, m - k, gi, gj, r1); });
+        }
         trsm_llu(gi, gj, r1, gi, gj + h, n - h);       // D <- L1^{-1} B1
-        trsm_run(gi + k, gj, m - k, gi, gj, r1);       // E <- C1 U1^{-1}
+        if (fork) {
+            check(hipEventRecord(ev_join, aux));
+            check(hipStreamWaitEvent(st, ev_join, 0));
+        } else {
+            trsm_run(gi + k, gj, m - k, gi, gj, r1);   // E <- C1 U1^{-1}
+        }
         MMProblem pb[3];
         pb[0] = mmprob(at(bF.i, bF.j), lda, bF.m, bF.n);
         mmpair(pb[0], 0, at(gi + r1, gj), lda, at(gi, gj + h), lda, r1);
