@@ -137,9 +137,14 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
     const int kmax = m < n ? m : n;
     const int steps = r_known >= 0 ? r_known : kmax;
     int r = steps;
-    bool ok = true;
-    int since = 0;
-    for (int s = 0; s < steps; ++s) {
+    bool ok = true, stop = false;
+    // Steps are taken in chunks of kchunk with a full-tile reduction between
+    // chunks, so that the loop over the steps of a chunk carries the tile
+    // registers through unchanged (a conditional reduction inside it makes
+    // the compiler keep two copies of the tile).
+    for (int s0 = 0; s0 < steps && !stop; s0 += kchunk) {
+    const int s1 = (steps - s0 > kchunk) ? s0 + kchunk : steps;
+    for (int s = s0; s < s1; ++s) {
         // ---- P1
         const double piv = mod_reduce(sh.row[s], mod);
         if (piv == 0.0) {
@@ -155,6 +160,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
             any = __syncthreads_or(any);
             ok = (any == 0) && (r_known < 0);
             r = s;
+            stop = true;
             break;
         }
         const double inv = bc_inverse(piv, mod, tab);
@@ -180,13 +186,6 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         for (int a = 0; a < R; ++a)
 #pragma unroll
             for (int b = 0; b < R; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
-        if (++since >= kchunk) {
-            since = 0;
-#pragma unroll
-            for (int a = 0; a < R; ++a)
-#pragma unroll
-                for (int b = 0; b < R; ++b) v[a][b] = mod_reduce(v[a][b], mod);
-        }
         if (s + 1 < steps) {
             // owners of row / column s+1 copy them to LDS; the register index
             // (s+1)/16 is wave-uniform and resolved by the switch
@@ -214,6 +213,13 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
 #undef PLUQ_BC_PUB
         }
         __syncthreads();
+    }
+    if (!stop && s1 < steps) {
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) v[a][b] = mod_reduce(v[a][b], mod);
+    }
     }
     if (ok && r_known >= 0 && r < kmax) {
         // the rank is known: the block left after it must be zero
