@@ -31,6 +31,8 @@
 // update is one FMA of symmetric residues on an exact integer-valued double,
 // an entry is reduced when it joins a pivot row or column, and every entry is
 // reduced after `kchunk` steps so that no accumulator exceeds 2^52.
+#include <cmath>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -69,6 +71,15 @@ struct BcShared {
     double Ub[BC_DIM];    // published pivot row (symmetric)
     double inv[BC_DIM];   // inverse of each pivot
 };
+
+// Symmetric reduction x - rint(x / p) p: for |x| < 2^52 the rounded quotient
+// is within one of the exact one and the fma is exact, so the result is
+// congruent to x with magnitude at most p/2 + 1, and zero exactly when p
+// divides x.  Three dependent operations instead of the five-plus fix-ups of
+// the canonical reduction, on the latency chain of every elimination step.
+__device__ __forceinline__ double sym_reduce(double x, const ModP &mod) {
+    return fma(-rint(x * mod.pinv), mod.p, x);
+}
 
 __device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const uint16_t *tab) {
     if (x == 0.0) return 0.0;
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
     const int s1 = (steps - s0 > kchunk) ? s0 + kchunk : steps;
     for (int s = s0; s < s1; ++s) {
         // ---- P1
-        const double piv = mod_reduce(sh.row[s], mod);
+        double piv = sym_reduce(sh.row[s], mod);
         if (piv == 0.0) {
             // zero pivot at (s, s): the identity order is right iff the rest is zero
             int any = 0;
@@ -155,7 +166,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
 #pragma unroll
                 for (int b = 0; b < R; ++b) {
                     const int i = ty + 16 * a, j = tx + 16 * b;
-                    if (i >= s && j >= s && i < m && j < n) any |= (mod_reduce(v[a][b], mod) != 0.0);
+                    if (i >= s && j >= s && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
                 }
             any = __syncthreads_or(any);
             ok = (any == 0) && (r_known < 0);
@@ -163,17 +174,18 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
             stop = true;
             break;
         }
+        if (piv < 0.0) piv += mod.p;   // canonical, for the inverse
         const double inv = bc_inverse(piv, mod, tab);
         if (tid < TILE) {
             const int j = tid;
-            const double u = mod_reduce(sh.row[j], mod);
-            sh.Ub[j] = (j > s && j < n) ? to_sym(u, mod) : 0.0;
+            const double u = sym_reduce(sh.row[j], mod);
+            sh.Ub[j] = (j > s && j < n) ? u : 0.0;
             if (j == 0) sh.inv[s] = inv;
         } else if (tid < 2 * TILE) {
             const int i = tid - TILE;
             const bool act = (i > s) && (i < m);
-            const double l = mod_mul(mod_reduce(sh.col[i], mod), inv, mod);
-            sh.Lb[i] = act ? to_sym(l, mod) : 0.0;
+            const double l = sym_reduce(sym_reduce(sh.col[i], mod) * inv, mod);
+            sh.Lb[i] = act ? l : 0.0;
         }
         __syncthreads();
         // ---- P2
@@ -218,7 +230,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
 #pragma unroll
         for (int a = 0; a < R; ++a)
 #pragma unroll
-            for (int b = 0; b < R; ++b) v[a][b] = mod_reduce(v[a][b], mod);
+            for (int b = 0; b < R; ++b) v[a][b] = sym_reduce(v[a][b], mod);
     }
     }
     if (ok && r_known >= 0 && r < kmax) {
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
 #pragma unroll
             for (int b = 0; b < R; ++b) {
                 const int i = ty + 16 * a, j = tx + 16 * b;
-                if (i >= r && j >= r && i < m && j < n) any |= (mod_reduce(v[a][b], mod) != 0.0);
+                if (i >= r && j >= r && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
             }
         ok = __syncthreads_or(any) == 0;
     }
@@ -436,6 +448,15 @@ hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int
                         int32_t *status, hipStream_t st) {
     if (m > BC_DIM || n > BC_DIM || m <= 0 || n <= 0 || kchunk < 1) return hipErrorInvalidValue;
     if (tab && p > BC_TAB_MAX) return hipErrorInvalidValue;
+    // Steps between full-tile reductions for this kernel's bound: entries
+    // start below p in magnitude, every step adds at most (p/2 + 1)^2 (the
+    // multipliers and pivot-row entries are symmetric reductions), and the
+    // sum must stay below 2^52.
+    {
+        const double h = std::floor(p / 2) + 1.0;
+        const double c = std::floor((4503599627370496.0 - 2.0 * p) / (h * h));
+        kchunk = c >= 1048576.0 ? 1048576 : (c < 1.0 ? 1 : (int)c);
+    }
     if (m <= 64 && n <= 64)
         return bc_lu_t<64>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, st);
     return bc_lu_t<128>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, st);
