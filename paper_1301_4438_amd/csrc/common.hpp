@@ -60,19 +60,29 @@ __device__ __forceinline__ double mod_inv(double a_, const ModP &m) {
     return (double)t;
 }
 
+// Symmetric reduction x - rint(x / p) p: for |x| < 2^52 the rounded quotient
+// is within one of the exact one and the fma is exact, so the result is
+// congruent to x with magnitude at most p/2 + 1, and zero exactly when p
+// divides x.  Three dependent operations instead of the canonical
+// reduction's five plus fix-ups: the form used on latency-bound chains.
+__device__ __forceinline__ double sym_reduce(double x, const ModP &m) {
+    return fma(-rint(x * m.pinv), m.p, x);
+}
+
 // Inverse of a non-zero canonical residue by Fermat's little theorem,
-// a^(p-2) mod p, square-and-multiply on exact float64 products: a fixed,
-// wave-uniform sequence of about 2 log2(p) modular products, shorter in
-// latency than the Euclidean algorithm's chain of integer divisions.
+// a^(p-2) mod p, square-and-multiply on exact float64 products of symmetric
+// residues: a fixed, wave-uniform sequence of about 2 log2(p) modular
+// products, shorter in latency than the Euclidean algorithm's chain of
+// integer divisions.  Returns the canonical inverse.
 __device__ __forceinline__ double inv_fermat(double a, const ModP &mod) {
     uint32_t e = (uint32_t)mod.p - 2u;
     double r = 1.0, b = a;
     while (e) {
-        if (e & 1u) r = mod_reduce(r * b, mod);
-        b = mod_reduce(b * b, mod);
+        if (e & 1u) r = sym_reduce(r * b, mod);
+        b = sym_reduce(b * b, mod);
         e >>= 1;
     }
-    return r;
+    return r < 0.0 ? r + mod.p : r;
 }
 
 __host__ __device__ inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }

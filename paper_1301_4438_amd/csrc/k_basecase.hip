@@ -72,15 +72,6 @@ struct BcShared {
     double inv[BC_DIM];   // inverse of each pivot
 };
 
-// Symmetric reduction x - rint(x / p) p: for |x| < 2^52 the rounded quotient
-// is within one of the exact one and the fma is exact, so the result is
-// congruent to x with magnitude at most p/2 + 1, and zero exactly when p
-// divides x.  Three dependent operations instead of the five-plus fix-ups of
-// the canonical reduction, on the latency chain of every elimination step.
-__device__ __forceinline__ double sym_reduce(double x, const ModP &mod) {
-    return fma(-rint(x * mod.pinv), mod.p, x);
-}
-
 __device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const uint16_t *tab) {
     if (x == 0.0) return 0.0;
     return tab ? (double)tab[(int)x] : mod_inv(x, mod);

@@ -23,7 +23,9 @@ namespace pluq {
 //   wave each, a lane per column, the diagonal inverses computed first);
 //   then the blocks below, by distance d = i - j = 1, 2, 3, all entries of a
 //   distance at once:  T = sum_{k=j}^{i-1} L_ik X_kj,  X_ij = -D_i T.
-// Products are of symmetric residues, reduced after every 16 terms.
+// Products are of symmetric residues, reduced (symmetric reduction) after
+// every 16 terms; the sums run as two independent chains and the blocks of
+// one distance together, since the kernel is bound by dependent latency.
 template <typename T, bool UPPER>
 __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t ldt, int r, T *W, ModP mod) {
     __shared__ double Ls[64][65];   // strict lower part (symmetric residues)
@@ -35,20 +37,22 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t
     const int nb = min(64, r - o);
     const T *Tq = Tm + (int64_t)o * ldt + o;
     {
-        double v[16];
+        // clamped addresses, so the 16 loads go out together
+        T raw[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = tid + 256 * q, a = e >> 6, b = e & 63;
-            v[q] = (a < nb && b < nb) ? to_f64(Tq[(int64_t)a * ldt + b]) : 0.0;
+            raw[q] = Tq[(int64_t)min(a, nb - 1) * ldt + min(b, nb - 1)];
         }
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int e = tid + 256 * q, a = e >> 6, b = e & 63;
+            const double v = (a < nb && b < nb) ? to_f64(raw[q]) : 0.0;
             // stored entry (a, b); the lower operand is L (UPPER: U^T)
             const int i = UPPER ? b : a, j = UPPER ? a : b;
-            if (i > j) Ls[i][j] = to_sym(v[q], mod);
+            if (i > j) Ls[i][j] = to_sym(v, mod);
             else if (i < j) Ls[i][j] = 0.0;
-            else dinv[i] = (!UPPER || a >= nb) ? 1.0 : v[q];
+            else dinv[i] = (!UPPER || a >= nb) ? 1.0 : v;
             Xs[a][b] = 0.0;
         }
     }
@@ -58,39 +62,62 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t
     const int lane = tid & 63, wv = tid >> 6;
     if (lane < 16) {
         const int base = 16 * wv, c = lane;
+        const double di = 1.0;
         double x[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
+            // two partial sums halve the dependent chain
+            double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
-            for (int k = 0; k < i; ++k) s = fma(-Ls[base + i][base + k], x[k], s);
-            x[i] = to_sym(mod_reduce(mod_reduce(s, mod) * dinv[base + i], mod), mod);
+            for (int k = 0; k < i; k += 2) {
+                s0 = fma(-Ls[base + i][base + k], x[k], s0);
+                if (k + 1 < i) s1 = fma(-Ls[base + i][base + k + 1], x[k + 1], s1);
+            }
+            const double s = sym_reduce(s0 + s1, mod);
+            x[i] = UPPER ? sym_reduce(s * dinv[base + i], mod) : s * di;
             Xs[base + i][base + c] = x[i];
         }
     }
     __syncthreads();
     const int a = tid >> 4, c = tid & 15;
+    // Off-diagonal 16 x 16 blocks by distance d = i - j; the blocks of one
+    // distance are independent and computed together (unrolled).
 #pragma unroll
     for (int d = 1; d < 4; ++d) {
+        double acc[3];
+#pragma unroll
         for (int b = 0; b < 4 - d; ++b) {
             const int j = b, i = b + d;
-            double acc = 0.0;
+            double sb = 0.0;
+#pragma unroll
             for (int k = j; k < i; ++k) {
-                double s = 0.0;
+                // 16 products of symmetric residues (each below 2^48), reduced
+                double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) s = fma(Ls[16 * i + a][16 * k + q], Xs[16 * k + q][16 * j + c], s);
-                acc += mod_reduce(s, mod);
+                for (int q = 0; q < 16; q += 2) {
+                    t0 = fma(Ls[16 * i + a][16 * k + q], Xs[16 * k + q][16 * j + c], t0);
+                    t1 = fma(Ls[16 * i + a][16 * k + q + 1], Xs[16 * k + q + 1][16 * j + c], t1);
+                }
+                sb += sym_reduce(t0 + t1, mod);
             }
-            Ts[b][a][c] = to_sym(mod_reduce(acc, mod), mod);
+            acc[b] = sb;
         }
-        __syncthreads();
-        for (int b = 0; b < 4 - d; ++b) {
-            const int j = b, i = b + d;
-            double s = 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) s = fma(Xs[16 * i + a][16 * i + q], Ts[b][q][c], s);
-            Xs[16 * i + a][16 * j + c] = to_sym(mod_reduce(-s, mod), mod);
+        for (int b = 0; b < 4 - d; ++b) Ts[b][a][c] = sym_reduce(acc[b], mod);
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 4 - d; ++b) {
+            const int i = b + d;
+            double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; q += 2) {
+                t0 = fma(Xs[16 * i + a][16 * i + q], Ts[b][q][c], t0);
+                t1 = fma(Xs[16 * i + a][16 * i + q + 1], Ts[b][q + 1][c], t1);
+            }
+            acc[b] = t0 + t1;
         }
+#pragma unroll
+        for (int b = 0; b < 4 - d; ++b) Xs[16 * (b + d) + a][16 * b + c] = sym_reduce(-acc[b], mod);
         __syncthreads();
     }
     T *Wq = W + (int64_t)blockIdx.x * 64 * 64;
