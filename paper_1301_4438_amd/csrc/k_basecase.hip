@@ -1,6 +1,6 @@
 // Base case of the recursion: the decomposition of a tile of at most
-// TILE x TILE entries (TILE = 64 or 128), done by one work-group of 256
-// threads.
+// TILE x TILE entries (TILE = 64 or 128), done by one work-group (256
+// threads; 512 for the elimination of a 128 x 128 tile).
 //
 // The output must be exactly the one Algorithm 1 would produce on the tile
 // (pivots in the order of its four recursive calls, non-pivot rows and
@@ -21,10 +21,11 @@
 // rank-profile pass is skipped.  The pivot order itself is computed on the
 // host between the two kernels (index bookkeeping only).
 //
-// Layout: thread (ty, tx) = (tid / 16, tid % 16) holds the R x R entries
-// (ty + 16a, tx + 16b), R = TILE / 16, in registers, so the shrinking trailing
-// block stays evenly spread over the threads.  Register indices that depend
-// on the step are resolved by a wave-uniform switch, never by indexing.
+// Layout: with NT threads, thread (ty, tx) = (tid / 16, tid % 16) holds the
+// entries (ty + SY a, tx + 16 b), SY = NT / 16, in registers (RA x RB of
+// them), so the shrinking trailing block stays evenly spread over the
+// threads.  Register indices that depend on the step are resolved by
+// wave-uniform switches, never by indexing.
 // Pivot inverses come from an LDS table of inverses when p <= 65536, else
 // from the extended Euclidean algorithm.
 // Arithmetic uses delayed reduction (Section 6) inside the elimination: the
@@ -39,6 +40,9 @@
 namespace pluq {
 
 constexpr int BC_THREADS = 256;
+// Threads of the elimination kernel for a tile: two waves per SIMD for the
+// 128 x 128 tile (32 entries per thread), one for the 64 x 64 tile.
+constexpr int bc_threads(int tile) { return tile > 64 ? 512 : 256; }
 constexpr int BC_DIM = 128;            // largest tile
 constexpr int BC_TAB_MAX = 65536;      // largest p with an LDS inverse table
 constexpr size_t BC_TAB_BYTES = BC_TAB_MAX * sizeof(uint16_t);
@@ -77,12 +81,13 @@ __device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const ui
     return tab ? (double)tab[(int)x] : mod_inv(x, mod);
 }
 
-template <typename T, int TILE>
-__global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, int m, int n,
-                                                           const int32_t *rmap, const int32_t *cmap,
-                                                           int r_known, ModP mod, int kchunk,
-                                                           const uint16_t *gtab, int32_t *status) {
-    constexpr int R = TILE / 16;
+template <typename T, int TILE, int NT>
+__global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int n, const int32_t *rmap,
+                                                   const int32_t *cmap, int r_known, ModP mod, int kchunk,
+                                                   const uint16_t *gtab, int32_t *status) {
+    constexpr int SY = NT / 16;       // row stride of a thread's entries
+    constexpr int RA = TILE / SY;     // rows per thread
+    constexpr int RB = TILE / 16;     // columns per thread
     extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ BcShared sh;
     const int tid = threadIdx.x;
@@ -94,32 +99,32 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         const int words = ((int)mod.p + 7) / 8;
         const uint4 *src = (const uint4 *)gtab;
         uint4 *dst = (uint4 *)dyn;
-        constexpr int PER = BC_TAB_MAX / 8 / BC_THREADS;   // 16-byte words per thread
+        constexpr int PER = BC_TAB_MAX / 8 / NT;           // 16-byte words per thread
         constexpr int CH = 8;                               // loads in flight per thread
 #pragma unroll
         for (int k0 = 0; k0 < PER; k0 += CH) {
             uint4 tmp[CH];
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const int w = tid + (k0 + k) * BC_THREADS;
+                const int w = tid + (k0 + k) * NT;
                 tmp[k] = (w < words) ? src[w] : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const int w = tid + (k0 + k) * BC_THREADS;
+                const int w = tid + (k0 + k) * NT;
                 if (w < words) dst[w] = tmp[k];
             }
         }
         tab = (const uint16_t *)dyn;
     }
 
-    double v[R][R];
+    double v[RA][RB];
 #pragma unroll
-    for (int a = 0; a < R; ++a) {
-        const int i = ty + 16 * a;
+    for (int a = 0; a < RA; ++a) {
+        const int i = ty + SY * a;
         const int64_t gi = (i < m) ? (rmap ? rmap[i] : i) : 0;
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
+        for (int b = 0; b < RB; ++b) {
             const int j = tx + 16 * b;
             double x = 0.0;
             if (i < m && j < n) x = to_f64(A[gi * lda + (cmap ? cmap[j] : j)]);
@@ -128,11 +133,11 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
     }
     if (ty == 0) {
 #pragma unroll
-        for (int b = 0; b < R; ++b) sh.row[tx + 16 * b] = v[0][b];
+        for (int b = 0; b < RB; ++b) sh.row[tx + 16 * b] = v[0][b];
     }
     if (tx == 0) {
 #pragma unroll
-        for (int a = 0; a < R; ++a) sh.col[ty + 16 * a] = v[a][0];
+        for (int a = 0; a < RA; ++a) sh.col[ty + SY * a] = v[a][0];
     }
     __syncthreads();
 
@@ -153,10 +158,10 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
             // zero pivot at (s, s): the identity order is right iff the rest is zero
             int any = 0;
 #pragma unroll
-            for (int a = 0; a < R; ++a)
+            for (int a = 0; a < RA; ++a)
 #pragma unroll
-                for (int b = 0; b < R; ++b) {
-                    const int i = ty + 16 * a, j = tx + 16 * b;
+                for (int b = 0; b < RB; ++b) {
+                    const int i = ty + SY * a, j = tx + 16 * b;
                     if (i >= s && j >= s && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
                 }
             any = __syncthreads_or(any);
@@ -180,58 +185,89 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         }
         __syncthreads();
         // ---- P2
-        double l[R], u[R];
+        double l[RA], u[RB];
 #pragma unroll
-        for (int a = 0; a < R; ++a) l[a] = sh.Lb[ty + 16 * a];
+        for (int a = 0; a < RA; ++a) l[a] = sh.Lb[ty + SY * a];
 #pragma unroll
-        for (int b = 0; b < R; ++b) u[b] = sh.Ub[tx + 16 * b];
+        for (int b = 0; b < RB; ++b) u[b] = sh.Ub[tx + 16 * b];
 #pragma unroll
-        for (int a = 0; a < R; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
-            for (int b = 0; b < R; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
+            for (int b = 0; b < RB; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
         if (s + 1 < steps) {
-            // owners of row / column s+1 copy them to LDS; the register index
-            // (s+1)/16 is wave-uniform and resolved by the switch
+            // owners of row / column s+1 copy them to LDS; the register
+            // indices (s+1)/SY and (s+1)/16 are wave-uniform and resolved by
+            // the switches
             const int t = s + 1;
-#define PLUQ_BC_PUB(Q)                                                                      \
-    if constexpr ((Q) < R) {                                                                \
-        if (ty == (t & 15)) {                                                               \
-            _Pragma("unroll") for (int b = 0; b < R; ++b) sh.row[tx + 16 * b] = v[(Q)][b];  \
-        }                                                                                   \
-        if (tx == (t & 15)) {                                                               \
-            _Pragma("unroll") for (int a = 0; a < R; ++a) sh.col[ty + 16 * a] = v[a][(Q)];  \
-        }                                                                                   \
+#define PLUQ_BC_ROW(Q)                                                                        \
+    if constexpr ((Q) < RA) {                                                                 \
+        if (ty == t % SY) {                                                                   \
+            _Pragma("unroll") for (int b = 0; b < RB; ++b) sh.row[tx + 16 * b] = v[(Q)][b];   \
+        }                                                                                     \
     }
-            switch (t >> 4) {
-            case 0: PLUQ_BC_PUB(0) break;
-            case 1: PLUQ_BC_PUB(1) break;
-            case 2: PLUQ_BC_PUB(2) break;
-            case 3: PLUQ_BC_PUB(3) break;
-            case 4: PLUQ_BC_PUB(4) break;
-            case 5: PLUQ_BC_PUB(5) break;
-            case 6: PLUQ_BC_PUB(6) break;
-            case 7: PLUQ_BC_PUB(7) break;
-            default: break;
+#define PLUQ_BC_COL(Q)                                                                        \
+    if constexpr ((Q) < RB) {                                                                 \
+        if (tx == (t & 15)) {                                                                 \
+            _Pragma("unroll") for (int a = 0; a < RA; ++a) sh.col[ty + SY * a] = v[a][(Q)];   \
+        }                                                                                     \
+    }
+            if constexpr (SY == 16) {
+                // one switch: row and column s+1 sit at the same register index
+                switch (t >> 4) {
+                case 0: PLUQ_BC_ROW(0) PLUQ_BC_COL(0) break;
+                case 1: PLUQ_BC_ROW(1) PLUQ_BC_COL(1) break;
+                case 2: PLUQ_BC_ROW(2) PLUQ_BC_COL(2) break;
+                case 3: PLUQ_BC_ROW(3) PLUQ_BC_COL(3) break;
+                case 4: PLUQ_BC_ROW(4) PLUQ_BC_COL(4) break;
+                case 5: PLUQ_BC_ROW(5) PLUQ_BC_COL(5) break;
+                case 6: PLUQ_BC_ROW(6) PLUQ_BC_COL(6) break;
+                case 7: PLUQ_BC_ROW(7) PLUQ_BC_COL(7) break;
+                default: break;
+                }
+            } else {
+                switch (t / SY) {
+                case 0: PLUQ_BC_ROW(0) break;
+                case 1: PLUQ_BC_ROW(1) break;
+                case 2: PLUQ_BC_ROW(2) break;
+                case 3: PLUQ_BC_ROW(3) break;
+                case 4: PLUQ_BC_ROW(4) break;
+                case 5: PLUQ_BC_ROW(5) break;
+                case 6: PLUQ_BC_ROW(6) break;
+                case 7: PLUQ_BC_ROW(7) break;
+                default: break;
+                }
+                switch (t >> 4) {
+                case 0: PLUQ_BC_COL(0) break;
+                case 1: PLUQ_BC_COL(1) break;
+                case 2: PLUQ_BC_COL(2) break;
+                case 3: PLUQ_BC_COL(3) break;
+                case 4: PLUQ_BC_COL(4) break;
+                case 5: PLUQ_BC_COL(5) break;
+                case 6: PLUQ_BC_COL(6) break;
+                case 7: PLUQ_BC_COL(7) break;
+                default: break;
+                }
             }
-#undef PLUQ_BC_PUB
+#undef PLUQ_BC_ROW
+#undef PLUQ_BC_COL
         }
         __syncthreads();
     }
     if (!stop && s1 < steps) {
 #pragma unroll
-        for (int a = 0; a < R; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
-            for (int b = 0; b < R; ++b) v[a][b] = sym_reduce(v[a][b], mod);
+            for (int b = 0; b < RB; ++b) v[a][b] = sym_reduce(v[a][b], mod);
     }
     }
     if (ok && r_known >= 0 && r < kmax) {
         // the rank is known: the block left after it must be zero
         int any = 0;
 #pragma unroll
-        for (int a = 0; a < R; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
-            for (int b = 0; b < R; ++b) {
-                const int i = ty + 16 * a, j = tx + 16 * b;
+            for (int b = 0; b < RB; ++b) {
+                const int i = ty + SY * a, j = tx + 16 * b;
                 if (i >= r && j >= r && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
             }
         ok = __syncthreads_or(any) == 0;
@@ -241,10 +277,10 @@ __global__ __launch_bounds__(BC_THREADS) void bc_lu_kernel(T *A, int64_t lda, in
         return;
     }
 #pragma unroll
-    for (int a = 0; a < R; ++a) {
-        const int i = ty + 16 * a;
+    for (int a = 0; a < RA; ++a) {
+        const int i = ty + SY * a;
 #pragma unroll
-        for (int b = 0; b < R; ++b) {
+        for (int b = 0; b < RB; ++b) {
             const int j = tx + 16 * b;
             if (i < m && j < n) {
                 double x = mod_reduce(v[a][b], mod);
@@ -383,12 +419,12 @@ hipError_t bc_init() {
     if (hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize,               \
                             (int)BC_TAB_BYTES) != hipSuccess)                                           \
         g_tab_ok = false;
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64>))
-    PLUQ_SETLDS((bc_lu_kernel<double, 64>))
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64>))
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128>))
-    PLUQ_SETLDS((bc_lu_kernel<double, 128>))
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128>))
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64, bc_threads(64)>))
+    PLUQ_SETLDS((bc_lu_kernel<double, 64, bc_threads(64)>))
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64, bc_threads(64)>))
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, bc_threads(128)>))
+    PLUQ_SETLDS((bc_lu_kernel<double, 128, bc_threads(128)>))
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, bc_threads(128)>))
 #undef PLUQ_SETLDS
     int dev = 0;
     hipDeviceProp_t prop;
@@ -418,15 +454,15 @@ static hipError_t bc_lu_t(int dtype, void *A, int64_t lda, int m, int n, const i
     const ModP md = make_mod(p);
     switch (dtype) {
     case DT_I64:
-        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE>), dim3(1), dim3(BC_THREADS), lds, st, (int64_t *)A, lda,
+        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (int64_t *)A, lda,
                     m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     case DT_F64:
-        PLUQ_LAUNCH((bc_lu_kernel<double, TILE>), dim3(1), dim3(BC_THREADS), lds, st, (double *)A, lda,
+        PLUQ_LAUNCH((bc_lu_kernel<double, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (double *)A, lda,
                     m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     case DT_I32:
-        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE>), dim3(1), dim3(BC_THREADS), lds, st, (int32_t *)A, lda,
+        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (int32_t *)A, lda,
                     m, n, rmap, cmap, r_known, md, kchunk, tab, status);
         break;
     default: return hipErrorInvalidValue;
