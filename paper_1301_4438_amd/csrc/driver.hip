@@ -554,8 +554,19 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
         mm(pb, 3);
     }
     {
+        // A non-empty block that fits a base-case tile needs no zero test
+        // first: the base case handles a zero tile itself (rank 0, identity
+        // order), so only larger blocks are resolved, and a node whose
+        // blocks are all small skips the synchronisation.
         Blk bl[3] = {bF, bG, bH};
-        resolve_zero(3, bl, zFGH, r1 > 0 ? gFGH : nullptr);
+        Zero zt[3];
+        for (int q = 0; q < 3; ++q) {
+            const bool small = bl[q].m > 0 && bl[q].n > 0 && bl[q].m <= cap && bl[q].n <= cap;
+            zt[q] = small ? Z_NONZERO : zFGH[q];   // Z_NONZERO here only means "not tested"
+        }
+        resolve_zero(3, bl, zt, r1 > 0 ? gFGH : nullptr);
+        for (int q = 0; q < 3; ++q)
+            if (!(bl[q].m > 0 && bl[q].n > 0 && bl[q].m <= cap && bl[q].n <= cap)) zFGH[q] = zt[q];
     }
 
     std::vector<int32_t> P2, Q2, P3, Q3;
@@ -593,7 +604,7 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
             pb.nzflag = d_stat + STAT_FLAG;
             pb.nzgen = gR;
             mm(&pb, 1);
-            resolve_zero(1, &bR, &zR, &gR);
+            if (bR.m > cap || bR.n > cap) resolve_zero(1, &bR, &zR, &gR);   // a small R goes to the base case as is
         } else {
             zR = zFGH[2];   // R is H itself
         }
