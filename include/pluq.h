@@ -96,6 +96,8 @@ typedef struct {
     int32_t batch_panel;        /* batched form: panel width 8 or 16 (0: 8; tuning only) */
     int32_t batch_groups;       /* batched form: persistent work-groups per compute unit
                                    (0: 4 for panel 8, 2 for panel 16; tuning only) */
+    int32_t no_speculation;     /* non-zero: no speculative first attempt (pluq_modp) and
+                                   no room for it in pluq_workspace_size */
 } pluq_opts;
 
 /* Human-readable name of a status code (static storage). */
@@ -122,6 +124,14 @@ size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p,
  *   opts     NULL for defaults (FP64 form, no validation).
  *   dWork    device workspace of work_bytes >= pluq_workspace_size(...),
  *            256-byte aligned; its contents are scratch.
+ * Unless opts->no_speculation is set, a matrix larger than one base-case
+ * tile whose copy fits in 1 GiB is first decomposed speculatively: every
+ * base-case tile is taken to be full rank in the identity order (a generic
+ * rank profile) without waiting for its result; the workspace holds a copy
+ * of A, and if any tile breaks the assumption A is restored from it and the
+ * exact recursion runs from the start.  The result is the same either way;
+ * only the time differs (faster on generic inputs, about one extra partial
+ * attempt otherwise).
  *   stream   HIP stream the work is ordered on (NULL: the null stream).  The
  *            call returns when the decomposition is complete.  Part of the
  *            work (the two independent triangular solves of each recursion

@@ -40,7 +40,8 @@ class PluqError(RuntimeError):
 class pluq_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("validate_entries", ctypes.c_int32),
                 ("cutoff_override", ctypes.c_int32), ("trsm_leaf_override", ctypes.c_int32),
-                ("batch_panel", ctypes.c_int32), ("batch_groups", ctypes.c_int32)]
+                ("batch_panel", ctypes.c_int32), ("batch_groups", ctypes.c_int32),
+                ("no_speculation", ctypes.c_int32)]
 
 
 class pluq_kernel_stat(ctypes.Structure):
@@ -129,8 +130,9 @@ def _stream(t):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _opts(form="fp64", validate=False, cutoff=0, trsm_leaf=0, batch_panel=0, batch_groups=0):
+def _opts(form="fp64", validate=False, cutoff=0, trsm_leaf=0, batch_panel=0, batch_groups=0, speculate=True):
     o = pluq_opts()
+    o.no_speculation = 0 if speculate else 1
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.validate_entries = int(bool(validate))
     o.cutoff_override = int(cutoff)

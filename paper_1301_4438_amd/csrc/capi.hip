@@ -142,16 +142,20 @@ int bc_cap() {
 }
 
 struct Layout {
-    size_t stat_off, idx_off, tab_off, w_off, w2_off, scratch_off, limb_off, total;
-    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes, limb_bytes;
+    size_t stat_off, idx_off, tab_off, w_off, w2_off, scratch_off, limb_off, spec_off, total;
+    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes, limb_bytes, spec_bytes;
 };
+
+// Largest matrix (bytes) for which the workspace holds a copy of A, taken
+// before a speculative decomposition so that a failed one can start again.
+constexpr size_t SPEC_MAX_BYTES = (size_t)1 << 30;
 
 // Diagonal-block inverses of a triangle of order r (TRSM).
 size_t trsm_w_bytes(int64_t r, size_t esz) {
     return (size_t)((r + TRSM_NB - 1) / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
 }
 
-Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form) {
+Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec) {
     Layout L;
     L.idx_elems = (size_t)(4 * (m + n) + 65536);
     const size_t full = (size_t)m * (size_t)n * esz;
@@ -168,7 +172,9 @@ Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form) {
     L.scratch_off = L.w2_off + align_up(L.w_bytes);
     L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0) ? limb_bytes_for(m, n, p) : 0;
     L.limb_off = L.scratch_off + align_up(L.scratch_bytes);
-    L.total = L.limb_off + align_up(L.limb_bytes);
+    L.spec_bytes = (spec && full <= SPEC_MAX_BYTES) ? full : 0;
+    L.spec_off = L.limb_off + align_up(L.limb_bytes);
+    L.total = L.spec_off + align_up(L.spec_bytes);
     return L;
 }
 
@@ -216,7 +222,7 @@ const char *pluq_version(void) { return "pluq-mi355x 0.1 (gfx950)"; }
 
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
-    return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64).total;
+    return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64, !(opts && opts->no_speculation)).total;
 }
 
 pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
@@ -230,7 +236,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
     const int form = opts ? opts->form : PLUQ_FORM_FP64;
     if ((s = form_check(form, p)) != PLUQ_OK) return s;
     const size_t esz = esize(dt);
-    const Layout L = layout(m, n, esz, p, form);
+    const Layout L = layout(m, n, esz, p, form, !(opts && opts->no_speculation));
     if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
     if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
 
@@ -288,7 +294,32 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
                     return PLUQ_ERR_RANGE;
                 }
             }
-            r = c.node(0, 0, m, n, Z_UNKNOWN, prow, pcol);
+            // Speculative first attempt when the workspace holds a copy of A
+            // and there is more than one base-case tile: every tile is taken
+            // to be full rank in the identity order (a generic rank profile,
+            // Section 5) without reading its result back.  The assumption is
+            // checked at every zero test and at the end; if it failed, A is
+            // restored and the exact recursion runs from the start.
+            bool done = false;
+            if (L.spec_bytes && (m > c.cap || n > c.cap)) {
+                char *backup = w + L.spec_off;
+                const double bytes = 2.0 * (double)m * (double)n * (double)esz;
+                c.launch(K_PERM, 0, bytes, [&] { return launch_gather2d(c.dt, dA, lda, backup, n, m, n, nullptr, nullptr, c.st); });
+                c.h_stat[STAT_SPEC] = 0;
+                c.check(hipMemcpyAsync(c.d_stat + STAT_SPEC, c.h_stat + STAT_SPEC, sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+                c.spec = true;
+                try {
+                    r = c.node(0, 0, m, n, Z_UNKNOWN, prow, pcol);
+                    c.check_spec();
+                    done = true;
+                } catch (const SpecFail &) {
+                    c.launch(K_PERM, 0, bytes, [&] { return launch_gather2d(c.dt, backup, n, dA, lda, m, n, nullptr, nullptr, c.st); });
+                    prow.clear();
+                    pcol.clear();
+                }
+                c.spec = false;
+            }
+            if (!done) r = c.node(0, 0, m, n, Z_UNKNOWN, prow, pcol);
         } else {
             prow.resize((size_t)m);
             pcol.resize((size_t)n);

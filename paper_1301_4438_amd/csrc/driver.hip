@@ -434,10 +434,20 @@ void zorder_from_rpm(int64_t m, int64_t n, const int32_t *rpm_col_in, std::vecto
 int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<int32_t> &prow,
                       std::vector<int32_t> &pcol) {
     stats.basecases++;
+    if (spec) {
+        // full rank in the identity order assumed; checked later
+        launch(K_BASE, 0, 2.0 * m * n * esz, [&] {
+            return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table,
+                                d_stat + STAT_BC, d_stat + STAT_SPEC, st);
+        });
+        iota(prow, m);
+        iota(pcol, n);
+        return std::min(m, n);
+    }
     // optimistic: the identity order (generic rank profile)
     const double tbytes = 2.0 * m * n * esz;
     launch(K_BASE, 0, tbytes, [&] {
-        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table, d_stat + STAT_BC, st);
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table, d_stat + STAT_BC, nullptr, st);
     });
     read_status(STAT_BC, 2);
     if (h_stat[STAT_BC + 1] == 1) {
@@ -459,7 +469,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     const int32_t *drow = upload(prow.data(), m);
     const int32_t *dcol = upload(pcol.data(), n);
     launch(K_BASE, 0, tbytes, [&] {
-        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table, d_stat + STAT_BC, st);
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table, d_stat + STAT_BC, nullptr, st);
     });
     // self-check of the ordered elimination: r non-zero pivots, zero remainder
     read_status(STAT_BC, 2);
@@ -486,9 +496,17 @@ void Ctx::resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens) {
         need = true;
     }
     if (!need) return;
-    read_status(STAT_FLAG, nb);
+    // in speculative mode the flags may rest on a failed assumption: the
+    // speculation flag is read with them and checked first
+    read_status(STAT_FLAG, spec ? STAT_SPEC + 1 : nb);
+    if (spec && h_stat[STAT_SPEC] != 0) throw SpecFail{};
     for (int b = 0; b < nb; ++b)
         if (z[b] == Z_UNKNOWN) z[b] = (h_stat[STAT_FLAG + b] == g[b]) ? Z_NONZERO : Z_ZERO;
+}
+
+void Ctx::check_spec() {
+    read_status(STAT_SPEC, 1);
+    if (h_stat[STAT_SPEC] != 0) throw SpecFail{};
 }
 
 // ------------------------------------------------------------------ node --

@@ -13,6 +13,9 @@ namespace pluq {
 struct DeviceError {
     hipError_t e;
 };
+// A speculative decomposition found a base-case tile that is not full rank
+// in the identity order (the caller restores the matrix and starts again).
+struct SpecFail {};
 
 struct Stats {
     int64_t nodes = 0, basecases = 0, launches = 0, syncs = 0;
@@ -56,6 +59,7 @@ struct Blk {
 
 // Layout of the int32 status area in device workspace.
 constexpr int64_t STAT_FLAG = 0;     // 8 zero-flag slots
+constexpr int64_t STAT_SPEC = 8;     // sticky flag: a speculated base case failed
 constexpr int64_t STAT_BC = 64;      // base-case status: r, ok / rpm columns
 constexpr int64_t STAT_WORDS = 64 + 2 + 16384 + 64;
 
@@ -90,6 +94,11 @@ struct Ctx {
     int32_t *h_stat = nullptr;
     int32_t gen = 0;
     Stats stats;
+    // Speculative mode: every base-case tile is taken to be full rank in the
+    // identity order without reading its result back; the tiles record a
+    // failed assumption in d_stat[STAT_SPEC], which is read with every zero
+    // test and at the end (SpecFail is thrown when it is set).
+    bool spec = false;
 
     void check(hipError_t e);
     // Issue one kernel launch (f returns its hipError_t), timed when the
@@ -132,6 +141,7 @@ struct Ctx {
     int64_t basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<int32_t> &prow,
                      std::vector<int32_t> &pcol);
     void resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens);
+    void check_spec();   // synchronising read of the speculation flag
     int64_t node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vector<int32_t> &prow,
                  std::vector<int32_t> &pcol);
 };

@@ -58,6 +58,19 @@ def test_workspace_size_monotone():
     assert pl.pluq_workspace_size(-1, 3, 1, 65521) == 0
 
 
+def test_workspace_size_speculation_copy():
+    """The speculative attempt keeps a copy of A in the workspace (up to
+    1 GiB); without speculation that region is not asked for."""
+    spec = pl.pluq_workspace_size(1000, 1200, 1, 65521, pl._opts("fp64"))
+    plain = pl.pluq_workspace_size(1000, 1200, 1, 65521, pl._opts("fp64", speculate=False))
+    assert spec - plain >= 1000 * 1200 * 8
+    assert spec - plain < 1000 * 1200 * 8 + 4096
+    big = 20000 * 20000 * 8   # above 1 GiB: no copy either way
+    assert pl.pluq_workspace_size(20000, 20000, 1, 65521, pl._opts("fp64")) == \
+        pl.pluq_workspace_size(20000, 20000, 1, 65521, pl._opts("fp64", speculate=False))
+    assert big > (1 << 30)
+
+
 def test_rank_profile_queries_host():
     P = [2, 0, 1, 3, 4, 5]
     Q = [0, 1]

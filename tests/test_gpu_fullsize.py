@@ -177,3 +177,31 @@ def test_concurrent_streams_vs_oracle(gpu_lib):
             P, Q, r, X = out[i]
             assert r == ro, i
             assert np.array_equal(P, Po) and np.array_equal(Q, Qo) and np.array_equal(X, Xo), i
+
+
+def test_speculation_on_off_identical(gpu_lib):
+    """The speculative first attempt (every base-case tile full rank in the
+    identity order) and the exact recursion give the same result on generic
+    inputs (where the attempt succeeds) and on inputs whose rank profile is
+    not generic (where it fails part-way and the matrix is restored and
+    decomposed again); both equal the oracle."""
+    import torch
+    p = 65521
+    cases = [("uniform", gen.uniform(700, 650, p, 21)),
+             ("xy", gen.xy_permuted(640, 700, 300, p, 22)),
+             ("planted", gen.planted_leu(600, 600, 400, p, 23)[0]),
+             ("zero_block", gen.zero_block(512, 768, 300, 100, p, 24)),
+             ("rank_one_tile", (gen.uniform(384, 1, p, 25) * gen.uniform(1, 384, p, 26)) % p)]
+    for name, A in cases:
+        note("speculation", name, A.shape)
+        Ad = torch.from_numpy(np.ascontiguousarray(A)).to(torch.float64).cuda()
+        Po, Qo, ro, Xo = oracle.pluqz(A, p)
+        for spec in (True, False):
+            X = Ad.clone()
+            P = torch.empty(A.shape[0], dtype=torch.int64, device="cuda")
+            Q = torch.empty(A.shape[1], dtype=torch.int64, device="cuda")
+            r = gpu_lib.pluq_modp(X, p, P, Q, gpu_lib._opts("fp64", speculate=spec))
+            torch.cuda.synchronize()
+            assert r == ro, (name, spec)
+            assert np.array_equal(P.cpu().numpy(), Po) and np.array_equal(Q.cpu().numpy(), Qo), (name, spec)
+            assert np.array_equal(X.cpu().numpy().astype(np.int64), Xo), (name, spec)
