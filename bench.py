@@ -44,12 +44,12 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the MM kernel per launch on this workload, from two
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
 # --no-comparisons` (FETCH_SIZE, then WRITE_SIZE).  FETCH_SIZE reads 0.5001x
-# the bytes of a plain 128 MiB device copy measured in the same runs and
-# WRITE_SIZE 1.0000x, so the fetch counter is scaled by 1.9996.  The figures
-# hold only for the kernel source they were taken on (sha256 prefix of
-# k_modmm.hip + common.hpp).
-MM_TRAFFIC = {"source_sha256_16": "1332d0fd1277774b",
-              "fetch_bytes_per_launch": 4271.40 * 1024, "write_bytes_per_launch": 832.21 * 1024}
+# the bytes of the plain 128 MiB device copies (restoring the inputs) in the
+# same runs and WRITE_SIZE 1.0000x, so the fetch counter is scaled by 1.9995.
+# The figures hold only for the kernel source they were taken on (sha256
+# prefix of k_modmm.hip + common.hpp).
+MM_TRAFFIC = {"source_sha256_16": "a97ad4867179fe2c",
+              "fetch_bytes_per_launch": 27888.72 * 1024, "write_bytes_per_launch": 3520.72 * 1024}
 
 
 def mm_source_hash() -> str:
