@@ -242,7 +242,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
 
     Stats stats;
     try {
-        if (!ensure_pinned(L.idx_elems, (size_t)std::max<int64_t>(m, n))) return PLUQ_ERR_NOMEM;
+        if (!ensure_pinned(L.idx_elems, (size_t)(m + n))) return PLUQ_ERR_NOMEM;
         Ctx c;
         c.dt = (int)dt;
         c.esz = esz;
@@ -326,17 +326,12 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             for (int64_t i = 0; i < m; ++i) prow[(size_t)i] = (int32_t)i;
             for (int64_t j = 0; j < n; ++j) pcol[(size_t)j] = (int32_t)j;
         }
-        // P and Q to the device (int64)
-        if (m > 0) {
-            for (int64_t i = 0; i < m; ++i) g_pin.pq[i] = prow[(size_t)i];
-            c.check(hipMemcpyAsync(dP, g_pin.pq, (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
-            c.sync();
-        }
-        if (n > 0) {
-            for (int64_t j = 0; j < n; ++j) g_pin.pq[j] = pcol[(size_t)j];
-            c.check(hipMemcpyAsync(dQ, g_pin.pq, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
-            c.sync();
-        }
+        // P and Q to the device (int64), one synchronisation for both
+        for (int64_t i = 0; i < m; ++i) g_pin.pq[i] = prow[(size_t)i];
+        for (int64_t j = 0; j < n; ++j) g_pin.pq[m + j] = pcol[(size_t)j];
+        if (m > 0) c.check(hipMemcpyAsync(dP, g_pin.pq, (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
+        if (n > 0) c.check(hipMemcpyAsync(dQ, g_pin.pq + m, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
+        if (m > 0 || n > 0) c.sync();
         *r_out = r;
         stats = c.stats;
         g_prof.resolve();

@@ -533,7 +533,9 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
 
     // PLUQ(A1)
     std::vector<int32_t> P1, Q1;
-    const int64_t r1 = node(gi, gj, k, h, Z_UNKNOWN, P1, Q1);
+    // (a speculative attempt does not test the leading quadrant for zero: a
+    // generic rank profile has none, and a zero quadrant fails its tiles)
+    const int64_t r1 = node(gi, gj, k, h, spec ? Z_NONZERO : Z_UNKNOWN, P1, Q1);
     perm_rows(gi, gj + h, k, n - h, P1);   // [B1; B2] <- P1^T A2
     perm_cols(gi + k, gj, m - k, h, Q1);   // [C1 C2] <- A3 Q1^T
 
