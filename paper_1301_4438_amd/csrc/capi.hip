@@ -300,13 +300,15 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             // Section 5) without reading its result back.  The assumption is
             // checked at every zero test and at the end; if it failed, A is
             // restored and the exact recursion runs from the start.
+            // the sticky flags start cleared
+            c.h_stat[STAT_SPEC] = 0;
+            c.h_stat[STAT_ERR] = 0;
+            c.check(hipMemcpyAsync(c.d_stat + STAT_SPEC, c.h_stat + STAT_SPEC, 2 * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
             bool done = false;
             if (L.spec_bytes && (m > c.cap || n > c.cap)) {
                 char *backup = w + L.spec_off;
                 const double bytes = 2.0 * (double)m * (double)n * (double)esz;
                 c.launch(K_PERM, 0, bytes, [&] { return launch_gather2d(c.dt, dA, lda, backup, n, m, n, nullptr, nullptr, c.st); });
-                c.h_stat[STAT_SPEC] = 0;
-                c.check(hipMemcpyAsync(c.d_stat + STAT_SPEC, c.h_stat + STAT_SPEC, sizeof(int32_t), hipMemcpyHostToDevice, c.st));
                 c.spec = true;
                 try {
                     r = c.node(0, 0, m, n, Z_UNKNOWN, prow, pcol);
@@ -331,7 +333,13 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         for (int64_t j = 0; j < n; ++j) g_pin.pq[m + j] = pcol[(size_t)j];
         if (m > 0) c.check(hipMemcpyAsync(dP, g_pin.pq, (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
         if (n > 0) c.check(hipMemcpyAsync(dQ, g_pin.pq + m, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
-        if (m > 0 || n > 0) c.sync();
+        if (m > 0 && n > 0) {
+            // with the last read-back: the base cases' error flag
+            c.read_status(STAT_ERR, 1);
+            c.check_err();
+        } else if (m > 0 || n > 0) {
+            c.sync();
+        }
         *r_out = r;
         stats = c.stats;
         g_prof.resolve();

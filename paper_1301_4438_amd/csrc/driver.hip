@@ -438,7 +438,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
         // full rank in the identity order assumed; checked later
         launch(K_BASE, 0, 2.0 * m * n * esz, [&] {
             return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table,
-                                d_stat + STAT_BC, d_stat + STAT_SPEC, st);
+                                d_stat + STAT_BC, d_stat + STAT_SPEC, nullptr, st);
         });
         iota(prow, m);
         iota(pcol, n);
@@ -446,14 +446,18 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     }
     // optimistic: the identity order (generic rank profile)
     const double tbytes = 2.0 * m * n * esz;
-    launch(K_BASE, 0, tbytes, [&] {
-        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table, d_stat + STAT_BC, nullptr, st);
-    });
-    read_status(STAT_BC, 2);
-    if (h_stat[STAT_BC + 1] == 1) {
-        iota(prow, m);
-        iota(pcol, n);
-        return h_stat[STAT_BC];
+    if (!skip_opt) {
+        launch(K_BASE, 0, tbytes, [&] {
+            return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table,
+                                d_stat + STAT_BC, nullptr, nullptr, st);
+        });
+        read_status(STAT_BC, 2);
+        if (h_stat[STAT_BC + 1] == 1) {
+            iota(prow, m);
+            iota(pcol, n);
+            return h_stat[STAT_BC];
+        }
+        skip_opt = true;
     }
     // general: rank profile matrix, then the pivot order, then the ordered LU
     launch(K_BASE, 0, 1.0 * m * n * esz,
@@ -466,14 +470,20 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     if ((int64_t)prow.size() != m || (int64_t)pcol.size() != n) throw DeviceError{hipErrorInvalidValue};
     require_permutation(prow);
     require_permutation(pcol);
+    // the identity order again: try the optimistic attempt on the next tile
+    bool ident = true;
+    for (int64_t i = 0; i < m && ident; ++i) ident = prow[(size_t)i] == i;
+    for (int64_t j = 0; j < n && ident; ++j) ident = pcol[(size_t)j] == j;
+    if (ident) skip_opt = false;
     const int32_t *drow = upload(prow.data(), m);
     const int32_t *dcol = upload(pcol.data(), n);
+    // The ordered elimination checks itself (r non-zero pivots, zero
+    // remainder) into the sticky error flag, which the host reads with the
+    // next read-back and at the end instead of waiting for it here.
     launch(K_BASE, 0, tbytes, [&] {
-        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table, d_stat + STAT_BC, nullptr, st);
+        return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table,
+                            d_stat + STAT_BC, nullptr, d_stat + STAT_ERR, st);
     });
-    // self-check of the ordered elimination: r non-zero pivots, zero remainder
-    read_status(STAT_BC, 2);
-    if (h_stat[STAT_BC + 1] != 1 || h_stat[STAT_BC] != r) throw DeviceError{hipErrorUnknown};
     return r;
 }
 
@@ -498,7 +508,8 @@ void Ctx::resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens) {
     if (!need) return;
     // in speculative mode the flags may rest on a failed assumption: the
     // speculation flag is read with them and checked first
-    read_status(STAT_FLAG, spec ? STAT_SPEC + 1 : nb);
+    read_status(STAT_FLAG, STAT_ERR + 1);
+    check_err();
     if (spec && h_stat[STAT_SPEC] != 0) throw SpecFail{};
     for (int b = 0; b < nb; ++b)
         if (z[b] == Z_UNKNOWN) z[b] = (h_stat[STAT_FLAG + b] == g[b]) ? Z_NONZERO : Z_ZERO;
@@ -507,6 +518,10 @@ void Ctx::resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens) {
 void Ctx::check_spec() {
     read_status(STAT_SPEC, 1);
     if (h_stat[STAT_SPEC] != 0) throw SpecFail{};
+}
+
+void Ctx::check_err() {
+    if (h_stat[STAT_ERR] != 0) throw DeviceError{hipErrorUnknown};
 }
 
 // ------------------------------------------------------------------ node --

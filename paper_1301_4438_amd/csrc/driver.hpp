@@ -60,6 +60,7 @@ struct Blk {
 // Layout of the int32 status area in device workspace.
 constexpr int64_t STAT_FLAG = 0;     // 8 zero-flag slots
 constexpr int64_t STAT_SPEC = 8;     // sticky flag: a speculated base case failed
+constexpr int64_t STAT_ERR = 9;      // sticky flag: an ordered base case failed its self-check
 constexpr int64_t STAT_BC = 64;      // base-case status: r, ok / rpm columns
 constexpr int64_t STAT_WORDS = 64 + 2 + 16384 + 64;
 
@@ -99,6 +100,10 @@ struct Ctx {
     // failed assumption in d_stat[STAT_SPEC], which is read with every zero
     // test and at the end (SpecFail is thrown when it is set).
     bool spec = false;
+    // Exact mode: after a tile failed the identity-order attempt, the next
+    // tiles go straight to the rank-profile search, until one comes out in
+    // the identity order (non-generic inputs tend to stay non-generic).
+    bool skip_opt = false;
 
     void check(hipError_t e);
     // Issue one kernel launch (f returns its hipError_t), timed when the
@@ -142,6 +147,7 @@ struct Ctx {
                      std::vector<int32_t> &pcol);
     void resolve_zero(int nb, const Blk *blk, Zero *z, const int32_t *gens);
     void check_spec();   // synchronising read of the speculation flag
+    void check_err();    // the error flag among the words just read back
     int64_t node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vector<int32_t> &prow,
                  std::vector<int32_t> &pcol);
 };

@@ -84,7 +84,8 @@ __device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const ui
 template <typename T, int TILE, int NT>
 __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int n, const int32_t *rmap,
                                                    const int32_t *cmap, int r_known, ModP mod, int kchunk,
-                                                   const uint16_t *gtab, int32_t *status, int32_t *specfail) {
+                                                   const uint16_t *gtab, int32_t *status, int32_t *specfail,
+                                                   int32_t *errflag) {
     constexpr int SY = NT / 16;       // row stride of a thread's entries
     constexpr int RA = TILE / SY;     // rows per thread
     constexpr int RB = TILE / 16;     // columns per thread
@@ -275,6 +276,8 @@ __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int
     // speculative use (the caller assumed a full-rank tile in the identity
     // order): record a failed assumption in the sticky flag
     if (specfail && tid == 0 && (!ok || r != kmax)) *specfail = 1;
+    // (errflag: the ordered elimination's self-check, read by the host later)
+    if (errflag && tid == 0 && !ok) *errflag = 1;
     if (!ok) {
         if (tid == 0) { status[0] = r; status[1] = 0; }
         return;
@@ -452,21 +455,21 @@ hipError_t launch_build_inv_table(uint16_t *tab, double p, hipStream_t st) {
 template <int TILE>
 static hipError_t bc_lu_t(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
                           const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
-                          int32_t *status, int32_t *specfail, hipStream_t st) {
+                          int32_t *status, int32_t *specfail, int32_t *errflag, hipStream_t st) {
     const size_t lds = tab ? BC_TAB_BYTES : 0;
     const ModP md = make_mod(p);
     switch (dtype) {
     case DT_I64:
         PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (int64_t *)A, lda,
-                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail);
+                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
         break;
     case DT_F64:
         PLUQ_LAUNCH((bc_lu_kernel<double, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (double *)A, lda,
-                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail);
+                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
         break;
     case DT_I32:
         PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (int32_t *)A, lda,
-                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail);
+                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -475,7 +478,7 @@ static hipError_t bc_lu_t(int dtype, void *A, int64_t lda, int m, int n, const i
 
 hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
                         const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
-                        int32_t *status, int32_t *specfail, hipStream_t st) {
+                        int32_t *status, int32_t *specfail, int32_t *errflag, hipStream_t st) {
     if (m > BC_DIM || n > BC_DIM || m <= 0 || n <= 0 || kchunk < 1) return hipErrorInvalidValue;
     if (tab && p > BC_TAB_MAX) return hipErrorInvalidValue;
     // Steps between full-tile reductions for this kernel's bound: entries
@@ -488,8 +491,8 @@ hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int
         kchunk = c >= 1048576.0 ? 1048576 : (c < 1.0 ? 1 : (int)c);
     }
     if (m <= 64 && n <= 64)
-        return bc_lu_t<64>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, st);
-    return bc_lu_t<128>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, st);
+        return bc_lu_t<64>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, errflag, st);
+    return bc_lu_t<128>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, errflag, st);
 }
 
 hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,

@@ -116,10 +116,11 @@ hipError_t launch_rangescan(int dtype, const void *A, int64_t lda, int64_t rows,
 // otherwise exactly r_known pivots are taken.  status[0] = r, status[1] = 1
 // on success (tile written back in packed order), 0 on failure (tile left
 // untouched).  specfail (optional): set to 1 unless the tile came out full
-// rank in the identity order (never cleared by the kernel).
+// rank in the identity order; errflag (optional): set to 1 on failure (both
+// sticky, never cleared by the kernel).
 hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
                         const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *inv_table,
-                        int32_t *status, int32_t *specfail, hipStream_t st);
+                        int32_t *status, int32_t *specfail, int32_t *errflag, hipStream_t st);
 // Table of inverses mod p (p <= 65536) used by bc_lu from LDS: bytes of the
 // device buffer (0 when the device cannot hold it in LDS or p is larger),
 // and the kernel that fills it.
