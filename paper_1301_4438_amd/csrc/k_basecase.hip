@@ -33,6 +33,7 @@
 // an entry is reduced when it joins a pivot row or column, and every entry is
 // reduced after `kchunk` steps so that no accumulator exceeds 2^52.
 #include <cmath>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -146,6 +147,98 @@ __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int
     const int steps = r_known >= 0 ? r_known : kmax;
     int r = steps;
     bool ok = true, stop = false;
+
+    // One elimination step s whose row and column s+1 sit in register row
+    // block QA and column block QB (compile-time constants, so the publish
+    // needs no switch).  Returns false at a zero pivot (r and ok set).
+    auto step = [&](int s, auto QA, auto QB) __attribute__((always_inline)) -> bool {
+        constexpr int qa = decltype(QA)::value, qb = decltype(QB)::value;
+        double piv = sym_reduce(sh.row[s], mod);
+        if (piv == 0.0) {
+            // zero pivot at (s, s): the identity order is right iff the rest is zero
+            int any = 0;
+#pragma unroll
+            for (int a = 0; a < RA; ++a)
+#pragma unroll
+                for (int b = 0; b < RB; ++b) {
+                    const int i = ty + SY * a, j = tx + 16 * b;
+                    if (i >= s && j >= s && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
+                }
+            any = __syncthreads_or(any);
+            ok = (any == 0) && (r_known < 0);
+            r = s;
+            return false;
+        }
+        if (piv < 0.0) piv += mod.p;   // canonical, for the inverse
+        const double inv = bc_inverse(piv, mod, tab);
+        if (tid < TILE) {
+            const int j = tid;
+            const double u = sym_reduce(sh.row[j], mod);
+            sh.Ub[j] = (j > s && j < n) ? u : 0.0;
+            if (j == 0) sh.inv[s] = inv;
+        } else if (tid < 2 * TILE) {
+            const int i = tid - TILE;
+            const bool act = (i > s) && (i < m);
+            const double l = sym_reduce(sym_reduce(sh.col[i], mod) * inv, mod);
+            sh.Lb[i] = act ? l : 0.0;
+        }
+        __syncthreads();
+        double l[RA], u[RB];
+#pragma unroll
+        for (int a = 0; a < RA; ++a) l[a] = sh.Lb[ty + SY * a];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) u[b] = sh.Ub[tx + 16 * b];
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int b = 0; b < RB; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
+        if (s + 1 < steps) {
+            const int t = s + 1;
+            if (ty == t % SY) {
+#pragma unroll
+                for (int b = 0; b < RB; ++b) sh.row[tx + 16 * b] = v[qa][b];
+            }
+            if (tx == (t & 15)) {
+#pragma unroll
+                for (int a = 0; a < RA; ++a) sh.col[ty + SY * a] = v[a][qb];
+            }
+        }
+        __syncthreads();
+        return true;
+    };
+
+    if (kchunk >= steps) {
+        // No full-tile reduction needed: the steps run in blocks of 16 by the
+        // index t = s + 1 of the row and column they publish, which sit in
+        // register column block t / 16 and row block t / SY, unrolled.
+#define PLUQ_BC_BLOCK(K)                                                                          \
+    if constexpr ((K) < RB) {                                                                     \
+        if (!stop) {                                                                              \
+            const int tlo = (K) * 16 < 1 ? 1 : (K) * 16;                                          \
+            const int thi = (K) * 16 + 16 <= steps ? (K) * 16 + 16 : steps + 1;                   \
+            for (int t = tlo; t < thi; ++t) {                                                     \
+                if (!step(t - 1, std::integral_constant<int, ((K) * 16) / SY>{},                  \
+                          std::integral_constant<int, (K)>{})) {                                  \
+                    stop = true;                                                                  \
+                    break;                                                                        \
+                }                                                                                 \
+            }                                                                                     \
+        }                                                                                         \
+    }
+        PLUQ_BC_BLOCK(0)
+        PLUQ_BC_BLOCK(1)
+        PLUQ_BC_BLOCK(2)
+        PLUQ_BC_BLOCK(3)
+        PLUQ_BC_BLOCK(4)
+        PLUQ_BC_BLOCK(5)
+        PLUQ_BC_BLOCK(6)
+        PLUQ_BC_BLOCK(7)
+#undef PLUQ_BC_BLOCK
+        // the last step of a full tile (s = TILE - 1 publishes nothing)
+        if (!stop && steps == 16 * RB) {
+            if (!step(steps - 1, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{})) stop = true;
+        }
+    } else {
     // Steps are taken in chunks of kchunk with a full-tile reduction between
     // chunks, so that the loop over the steps of a chunk carries the tile
     // registers through unchanged (a conditional reduction inside it makes
@@ -259,6 +352,7 @@ __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int
         for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < RB; ++b) v[a][b] = sym_reduce(v[a][b], mod);
+    }
     }
     }
     if (ok && r_known >= 0 && r < kmax) {
