@@ -120,6 +120,24 @@ def _time_decomp(pl, A, p, form, reps=2):
     return r, best
 
 
+def basecase_figures(bc, n):
+    """Base-case kernel figures from the profiled step: average launch time,
+    time per pivot of a full 128 x 128 tile, and its algorithmic work
+    (2/3 t^3 flops of an LU of a t x t tile) against one compute unit's share
+    of the FP64 peak (the kernel runs on one work-group by design)."""
+    if not bc or not bc["launches"]:
+        return None
+    t = 128
+    ms = bc["ms"] / bc["launches"]
+    flops = 2.0 / 3.0 * t ** 3
+    gflops = flops / (ms * 1e-3) / 1e9
+    cu_peak_gflops = FP64_MFMA_PEAK_TFLOPS * 1e3 / 256
+    return {"kernel": "bc_lu (128 x 128 tile, 512 threads, one work-group)", "bound": "latency",
+            "launches": bc["launches"], "avg_launch_ms": ms, "us_per_pivot": ms * 1e3 / t,
+            "algorithmic_flops_per_launch": flops, "achieved_gflops": gflops,
+            "one_cu_fp64_peak_gflops": cu_peak_gflops, "frac_of_one_cu": gflops / cu_peak_gflops}
+
+
 def large_update(pl, seed):
     """One large update on its own, 8192 x 8192 x 4096 (one INT8 launch
     deep), in every form: time per call and the fraction of the form's peak."""
@@ -171,7 +189,14 @@ def comparisons(pl, c2_pristine, seed):
         r, t = _time_decomp(pl, A, 65521, "int8")
         secs += t
         ops += 2.0 * A.shape[0] * A.shape[1] * r
-    out["c2_4096_pair_int8"] = {"ms_per_step": secs * 1e3, "gops": ops / secs / 1e9}
+    out["c2_4096_pair_int8"] = {"ms_per_step": secs * 1e3, "gops": ops / secs / 1e9,
+                                "note": "the two decompositions one after the other"}
+    # its counterpart: the FP64 form, also one after the other
+    secs64 = 0.0
+    for A in c2_pristine:
+        _, t = _time_decomp(pl, A, 65521, "fp64")
+        secs64 += t
+    out["c2_4096_pair_fp64_sequential"] = {"ms_per_step": secs64 * 1e3, "gops": ops / secs64 / 1e9}
     # 16384^2 rank 12000, every form; MM-kernel rate of the INT8 form
     for p, forms in [(65521, ["fp64", "int8"]), (251, ["fp64", "int8", "fp32"])]:
         A = gen.xy_permuted(16384, 16384, 12000, p, seed, device="cuda").to(torch.float64)
@@ -340,6 +365,11 @@ def main():
                      "profiled_steps": 1,
                      "algorithmic_bytes_per_launch": mm["bytes"] / max(mm["launches"], 1),
                      "traffic": traffic},
+        # By device time the base case is the largest single kernel: one
+        # work-group per 128 x 128 tile (one compute unit), its pivots in
+        # sequence, so it is bound by the latency of each pivot's exchange,
+        # not by a throughput roof; its figures per launch and per pivot.
+        "latency_bound_basecase": basecase_figures(prof.get("basecase"), pristine[0].shape[0]),
         "device_ms_per_class_in_profiled_step": {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]},
         "launches_per_class_in_profiled_step": {c: v["launches"] for c, v in prof.items() if v["launches"]},
         "library_stats_last_call": stats,
