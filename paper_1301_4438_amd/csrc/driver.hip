@@ -446,18 +446,19 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     }
     // optimistic: the identity order (generic rank profile)
     const double tbytes = 2.0 * m * n * esz;
-    if (!skip_opt) {
+    if (opt_fails < 2) {
         launch(K_BASE, 0, tbytes, [&] {
             return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table,
                                 d_stat + STAT_BC, nullptr, nullptr, st);
         });
         read_status(STAT_BC, 2);
         if (h_stat[STAT_BC + 1] == 1) {
+            opt_fails = 0;
             iota(prow, m);
             iota(pcol, n);
             return h_stat[STAT_BC];
         }
-        skip_opt = true;
+        ++opt_fails;
     }
     // general: rank profile matrix, then the pivot order, then the ordered LU
     launch(K_BASE, 0, 1.0 * m * n * esz,
@@ -474,7 +475,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     bool ident = true;
     for (int64_t i = 0; i < m && ident; ++i) ident = prow[(size_t)i] == i;
     for (int64_t j = 0; j < n && ident; ++j) ident = pcol[(size_t)j] == j;
-    if (ident) skip_opt = false;
+    if (ident) opt_fails = 0;
     const int32_t *drow = upload(prow.data(), m);
     const int32_t *dcol = upload(pcol.data(), n);
     // The ordered elimination checks itself (r non-zero pivots, zero

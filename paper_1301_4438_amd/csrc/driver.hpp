@@ -100,10 +100,11 @@ struct Ctx {
     // failed assumption in d_stat[STAT_SPEC], which is read with every zero
     // test and at the end (SpecFail is thrown when it is set).
     bool spec = false;
-    // Exact mode: after a tile failed the identity-order attempt, the next
-    // tiles go straight to the rank-profile search, until one comes out in
-    // the identity order (non-generic inputs tend to stay non-generic).
-    bool skip_opt = false;
+    // Exact mode: after two tiles in a row failed the identity-order attempt,
+    // the next tiles go straight to the rank-profile search, until one comes
+    // out in the identity order (inputs far from generic stay so; a single
+    // failure, as with a small p where tiles fail at random, does not switch).
+    int opt_fails = 0;
 
     void check(hipError_t e);
     // Issue one kernel launch (f returns its hipError_t), timed when the
