@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpluq.so")
@@ -147,16 +148,22 @@ def _check(st, where):
         raise PluqError(st, where)
 
 
-_ws_cache = {}
+# Workspace buffers kept between calls, per host thread and device: calls
+# from different threads may run concurrently (each on its own stream), so
+# they must not share scratch memory.
+_ws_local = threading.local()
 
 
 def _workspace(device, nbytes):
     import torch
+    cache = getattr(_ws_local, "cache", None)
+    if cache is None:
+        cache = _ws_local.cache = {}
     key = str(device)
-    buf = _ws_cache.get(key)
+    buf = cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
-        _ws_cache[key] = buf
+        cache[key] = buf
     return buf
 
 
