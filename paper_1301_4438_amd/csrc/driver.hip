@@ -462,7 +462,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     }
     // general: rank profile matrix, then the pivot order, then the ordered LU
     launch(K_BASE, 0, 1.0 * m * n * esz,
-           [&] { return launch_bc_rpm(dt, at(gi, gj), lda, (int)m, (int)n, (double)p, kchunk, d_stat + STAT_BC, st); });
+           [&] { return launch_bc_rpm(dt, at(gi, gj), lda, (int)m, (int)n, (double)p, kchunk, inv_table, d_stat + STAT_BC, st); });
     read_status(STAT_BC, 1 + m);
     const int64_t r = h_stat[STAT_BC];
     for (int64_t i = 0; i < m; ++i)

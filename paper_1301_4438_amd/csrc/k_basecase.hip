@@ -395,18 +395,47 @@ __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int
 // Rank profile matrix of the tile: status[0] = r, status[1 + i] = pivot
 // column of row i or -1.  Rows are processed in order; the pivot of row i is
 // the first non-zero entry of the reduced row among the columns that are not
-// yet pivot columns.  (Taken for non-generic tiles only.)
-template <typename T>
-__global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t lda, int m, int n,
-                                                            ModP mod, int kchunk, int32_t *status) {
+// yet pivot columns.  (Taken for non-generic tiles only.)  Same register
+// layout as the elimination kernel with 256 threads (R x R entries per
+// thread); rows run in blocks of 16 so that the row owners' register row is
+// a compile-time index; each thread keeps the pivot columns among its own
+// columns as a bit mask; the pivot inverse comes from the LDS table when p
+// <= 65536; the tile is reduced (symmetric reduction) after every block of 16
+// rows, or after every pivot when RED1 (p close to 2^25).
+template <typename T, bool RED1>
+__global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t lda, int m, int n, ModP mod,
+                                                            const uint16_t *gtab, int32_t *status) {
     constexpr int R = 8;
+    extern __shared__ __align__(16) unsigned char dyn[];
     __shared__ double Lb[BC_DIM];
     __shared__ double Ub[2][BC_DIM];
     __shared__ int mins[2][16];
     __shared__ double s_inv;
-    __shared__ unsigned char dead[BC_DIM];
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
+    const uint16_t *tab = nullptr;
+    if (gtab) {
+        const int words = ((int)mod.p + 7) / 8;
+        const uint4 *src = (const uint4 *)gtab;
+        uint4 *dst = (uint4 *)dyn;
+        constexpr int PER = BC_TAB_MAX / 8 / BC_THREADS;
+        constexpr int CH = 8;
+#pragma unroll
+        for (int k0 = 0; k0 < PER; k0 += CH) {
+            uint4 tmp[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int w = tid + (k0 + k) * BC_THREADS;
+                tmp[k] = (w < words) ? src[w] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int w = tid + (k0 + k) * BC_THREADS;
+                if (w < words) dst[w] = tmp[k];
+            }
+        }
+        tab = (const uint16_t *)dyn;
+    }
     double v[R][R];
 #pragma unroll
     for (int a = 0; a < R; ++a)
@@ -415,27 +444,29 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
             const int i = ty + 16 * a, j = tx + 16 * b;
             v[a][b] = (i < m && j < n) ? to_f64(A[(int64_t)i * lda + j]) : 0.0;
         }
-    if (tid < BC_DIM) dead[tid] = 0;
     if (tid < m) status[1 + tid] = -1;
+    uint32_t dead = 0;   // bit b: column tx + 16 b is a pivot column
     __syncthreads();
-    int r = 0, since = 0;
-    for (int i = 0; i < m; ++i) {
+    int r = 0;
+    auto reduce_all = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) v[a][b] = sym_reduce(v[a][b], mod);
+    };
+    auto row_step = [&](int i, auto AI) __attribute__((always_inline)) {
+        constexpr int ai = decltype(AI)::value;
         const int buf = i & 1;
-        const int ai = i >> 4;
         if (ty == (i & 15)) {
             int first = 1 << 30;
 #pragma unroll
             for (int b = 0; b < R; ++b) {
                 const int j = tx + 16 * b;
-                if (j < n && !dead[j]) {
-#pragma unroll
-                    for (int a = 0; a < R; ++a)
-                        if (a == ai) {
-                            const double u = mod_reduce(v[a][b], mod);
-                            v[a][b] = u;
-                            Ub[buf][j] = to_sym(u, mod);
-                            if (u != 0.0 && j < first) first = j;
-                        }
+                if (j < n && !((dead >> b) & 1u)) {
+                    const double u = sym_reduce(v[ai][b], mod);
+                    v[ai][b] = u;
+                    Ub[buf][j] = u;
+                    if (u != 0.0 && j < first) first = j;
                 }
             }
             mins[buf][tx] = first;
@@ -444,36 +475,35 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
         int jc = 1 << 30;
 #pragma unroll
         for (int t = 0; t < 16; ++t) jc = min(jc, mins[buf][t]);
-        if (jc >= n) continue;   // dependent row (uniform)
+        if (jc >= n) return;   // dependent row (uniform)
         ++r;
+        const int bj = jc >> 4;
         if (ty == (i & 15) && tx == (jc & 15)) {
-            const int bj = jc >> 4;
+            double pv = 0.0;
 #pragma unroll
-            for (int a = 0; a < R; ++a)
-#pragma unroll
-                for (int b = 0; b < R; ++b)
-                    if (a == ai && b == bj) s_inv = mod_inv(v[a][b], mod);
-            dead[jc] = 1;
+            for (int b = 0; b < R; ++b)
+                if (b == bj) pv = v[ai][b];
+            if (pv < 0.0) pv += mod.p;   // canonical, for the inverse
+            s_inv = tab ? (double)tab[(int)pv] : mod_inv(pv, mod);
             status[1 + i] = jc;
         }
+        if (tx == (jc & 15)) dead |= 1u << bj;
         __syncthreads();
         const double inv = s_inv;
         if (tx == (jc & 15)) {
-            const int bj = jc >> 4;
 #pragma unroll
             for (int a = 0; a < R; ++a) {
                 const int k = ty + 16 * a;
                 if (k > i && k < m) {
+                    double c = 0.0;
 #pragma unroll
                     for (int b = 0; b < R; ++b)
-                        if (b == bj) Lb[k] = to_sym(mod_mul(mod_reduce(v[a][b], mod), inv, mod), mod);
+                        if (b == bj) c = v[a][b];
+                    Lb[k] = sym_reduce(sym_reduce(c, mod) * inv, mod);
                 }
             }
         }
         __syncthreads();
-        ++since;
-        const bool red = since >= kchunk;
-        if (red) since = 0;
 #pragma unroll
         for (int a = 0; a < R; ++a) {
             const int k = ty + 16 * a;
@@ -482,18 +512,31 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
 #pragma unroll
                 for (int b = 0; b < R; ++b) {
                     const int j = tx + 16 * b;
-                    if (j < n && !dead[j]) {
-                        double x = fma(-l, Ub[buf][j], v[a][b]);
-                        if (red) x = mod_reduce(x, mod);
-                        v[a][b] = x;
-                    }
+                    if (j < n && !((dead >> b) & 1u)) v[a][b] = fma(-l, Ub[buf][j], v[a][b]);
                 }
             }
         }
-        // Ub is double-buffered: the next row's owners fill the other half
-        // before its first barrier.  Lb, s_inv and dead are rewritten only
-        // after that barrier, which every thread reaches after this update.
+        if (RED1) reduce_all();
+        // Ub and mins are double-buffered: the next row's owners fill the
+        // other half before its first barrier.  Lb and s_inv are rewritten
+        // only after that barrier, which every thread reaches after this
+        // update.
+    };
+#define PLUQ_RPM_BLOCK(K)                                                                         \
+    {                                                                                             \
+        const int ihi = (K) * 16 + 16 < m ? (K) * 16 + 16 : m;                                    \
+        for (int i = (K) * 16; i < ihi; ++i) row_step(i, std::integral_constant<int, (K)>{});     \
+        if (!RED1) reduce_all();                                                                  \
     }
+    PLUQ_RPM_BLOCK(0)
+    PLUQ_RPM_BLOCK(1)
+    PLUQ_RPM_BLOCK(2)
+    PLUQ_RPM_BLOCK(3)
+    PLUQ_RPM_BLOCK(4)
+    PLUQ_RPM_BLOCK(5)
+    PLUQ_RPM_BLOCK(6)
+    PLUQ_RPM_BLOCK(7)
+#undef PLUQ_RPM_BLOCK
     __syncthreads();
     if (tid == 0) status[0] = r;
 }
@@ -525,6 +568,12 @@ hipError_t bc_init() {
     PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, bc_threads(128)>))
     PLUQ_SETLDS((bc_lu_kernel<double, 128, bc_threads(128)>))
     PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, bc_threads(128)>))
+    PLUQ_SETLDS((bc_rpm_kernel<int64_t, false>))
+    PLUQ_SETLDS((bc_rpm_kernel<double, false>))
+    PLUQ_SETLDS((bc_rpm_kernel<int32_t, false>))
+    PLUQ_SETLDS((bc_rpm_kernel<int64_t, true>))
+    PLUQ_SETLDS((bc_rpm_kernel<double, true>))
+    PLUQ_SETLDS((bc_rpm_kernel<int32_t, true>))
 #undef PLUQ_SETLDS
     int dev = 0;
     hipDeviceProp_t prop;
@@ -590,23 +639,29 @@ hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int
 }
 
 hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,
-                         int32_t *status, hipStream_t st) {
+                         const uint16_t *tab, int32_t *status, hipStream_t st) {
     if (m > BC_DIM || n > BC_DIM || m <= 0 || n <= 0 || kchunk < 1) return hipErrorInvalidValue;
+    if (tab && p > BC_TAB_MAX) return hipErrorInvalidValue;
+    // pivots between reductions for symmetric entries: every pivot adds at
+    // most (p/2 + 1)^2 to an entry that starts below p in magnitude
+    const double h = std::floor(p / 2) + 1.0;
+    const bool red1 = (4503599627370496.0 - 2.0 * p) / (h * h) < 16.0;
+    const size_t lds = tab ? BC_TAB_BYTES : 0;
+    const ModP md = make_mod(p);
+#define PLUQ_RPM(TT)                                                                                     \
+    if (red1)                                                                                            \
+        PLUQ_LAUNCH((bc_rpm_kernel<TT, true>), dim3(1), dim3(BC_THREADS), lds, st, (const TT *)A, lda, m, n, md, \
+                    tab, status);                                                                        \
+    else                                                                                                 \
+        PLUQ_LAUNCH((bc_rpm_kernel<TT, false>), dim3(1), dim3(BC_THREADS), lds, st, (const TT *)A, lda, m, n, md, \
+                    tab, status);
     switch (dtype) {
-    case DT_I64:
-        PLUQ_LAUNCH(bc_rpm_kernel<int64_t>, dim3(1), dim3(BC_THREADS), 0, st, (const int64_t *)A, lda, m, n,
-                    make_mod(p), kchunk, status);
-        break;
-    case DT_F64:
-        PLUQ_LAUNCH(bc_rpm_kernel<double>, dim3(1), dim3(BC_THREADS), 0, st, (const double *)A, lda, m, n,
-                    make_mod(p), kchunk, status);
-        break;
-    case DT_I32:
-        PLUQ_LAUNCH(bc_rpm_kernel<int32_t>, dim3(1), dim3(BC_THREADS), 0, st, (const int32_t *)A, lda, m, n,
-                    make_mod(p), kchunk, status);
-        break;
+    case DT_I64: PLUQ_RPM(int64_t) break;
+    case DT_F64: PLUQ_RPM(double) break;
+    case DT_I32: PLUQ_RPM(int32_t) break;
     default: return hipErrorInvalidValue;
     }
+#undef PLUQ_RPM
     return hipGetLastError();
 }
 

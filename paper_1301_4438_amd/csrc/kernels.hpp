@@ -131,8 +131,9 @@ constexpr size_t BC_TABLE_RESERVE = 65536 * sizeof(uint16_t);
 hipError_t launch_build_inv_table(uint16_t *tab, double p, hipStream_t st);
 // Base case, rank profile matrix of the m x n tile: status[0] = r and
 // status[1 + i] = pivot column of row i or -1.  The tile is not modified.
+// inv_table: as for bc_lu (or null).
 hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,
-                         int32_t *status, hipStream_t st);
+                         const uint16_t *inv_table, int32_t *status, hipStream_t st);
 int bc_capacity();        // maximum rows (and columns) of a base-case tile
 hipError_t bc_init();     // one-time set-up of the base-case kernels
 

@@ -194,3 +194,17 @@ def test_generator_device_product_matches_host(gpu_lib):
         a = gen.xy_permuted(m, n, r, p, seed=4)
         b = gen.xy_permuted(m, n, r, p, seed=4, device="cuda").cpu().numpy()
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["int64", "float64"])
+def test_pluq_large_modulus(gpu_lib, dtype):
+    """p = 33554393, just below the FP64 form's bound 2^25: the base case and
+    the rank-profile search reduce after every pivot there; generic and
+    non-generic tiles against the oracle."""
+    g = np.random.default_rng(2 ** 25)
+    p = 33554393
+    for kind, (m, n) in [("uniform", (200, 180)), ("planted", (150, 260)), ("lowrank", (300, 140)),
+                         ("zeroband", (130, 130)), ("sparse", (97, 240))]:
+        A = _mixed_inputs(g, m, n, p, kind)
+        note("pluq large p", kind, m, n, dtype)
+        _check_pluq(gpu_lib, A, p, dtype=dtype)
