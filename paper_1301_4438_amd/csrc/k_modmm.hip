@@ -19,8 +19,7 @@
 // B row-major, both padded); global loads are lane-contiguous row segments;
 // the next panel is fetched into registers while the current one is used.
 // 64 x 64 and 32 x 32 tiles use BK = 64, so an update with K <= 64 (the
-// leaves of the triangular solves and the deep Schur updates) needs a single
-// load phase.
+// deep Schur updates) needs a single load phase.
 //
 // The same kernel in float32 (CT = float, v_mfma_f32_16x16x4_f32) is the
 // FP32 form for small moduli: a float32 sum of integers is exact while it

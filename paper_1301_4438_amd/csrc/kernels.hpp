@@ -21,10 +21,12 @@ struct MMProblem {
     int32_t M, N;
     int32_t *nzflag;   // if non-null: set to nzgen when an output element is non-zero
     int32_t nzgen;
-    int32_t inplace;   // C is also an operand (a triangular-solve leaf):
-                       // 1 = C is the B operand (M <= 64), 2 = C is the A
-                       // operand (N <= 64).  The tile then spans all of M
-                       // (or N), so no work-group writes what another reads.
+    int32_t inplace;   // C is also an operand (an in-place product such as
+                       // B <- B - W.B): 1 = C is the B operand (M <= 64),
+                       // 2 = C is the A operand (N <= 64).  The tile then
+                       // spans all of M (or N), so no work-group writes what
+                       // another reads.  (The solves now use their own leaf
+                       // kernel; the mode stays available.)
     int32_t tileStart; // filled by the launcher
     int32_t tilesN;    // filled by the launcher
 };
