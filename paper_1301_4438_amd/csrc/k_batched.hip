@@ -144,12 +144,11 @@ __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const Mo
             }
             const double inv = inv_fermat(piv, mod);
             for (int i = t + 1 + tid; i < pr; i += BT) {
-                const double l = mod_reduce((double)L.pan[i * KB + t] * inv, mod);
-                L.pan[i * KB + t] = (int32_t)l;
-                const double ls = sym(l, mod);
+                const double ls = sym_reduce((double)L.pan[i * KB + t] * inv, mod);
+                L.pan[i * KB + t] = (int32_t)(ls < 0.0 ? ls + mod.p : ls);
                 for (int u = t + 1; u < kb; ++u) {
-                    const double x = fma(-ls, sym((double)L.pan[t * KB + u], mod), (double)L.pan[i * KB + u]);
-                    L.pan[i * KB + u] = (int32_t)mod_reduce(x, mod);
+                    const double x = sym_reduce(fma(-ls, sym((double)L.pan[t * KB + u], mod), (double)L.pan[i * KB + u]), mod);
+                    L.pan[i * KB + u] = (int32_t)(x < 0.0 ? x + mod.p : x);
                 }
             }
             __syncthreads();
@@ -177,14 +176,21 @@ __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const Mo
                     double acc = xs[t];
 #pragma unroll
                     for (int u = 0; u < t; ++u) acc = fma(-sym((double)L.pan[t * KB + u], mod), xs[u], acc);
-                    const double x = mod_reduce(acc, mod);
-                    L.urow[t * BMAX + c] = (int32_t)x;
-                    xs[t] = sym(x, mod);
+                    const double xsym = sym_reduce(acc, mod);
+                    L.urow[t * BMAX + c] = (int32_t)(xsym < 0.0 ? xsym + mod.p : xsym);
+                    xs[t] = xsym;
                 }
             }
 #pragma unroll
             for (int t = 0; t < KB; ++t)
                 if (t < kbe) A[(int64_t)(s + t) * lda + c0 + c] = from_f64<T>((double)L.urow[t * BMAX + c]);
+        }
+        __syncthreads();
+        // The panel's multipliers below the pivots as symmetric residues,
+        // once, for the trailing update (they are already written back).
+        for (int e = tid; e < (pr - kbe) * KB; e += BT) {
+            const int i = kbe + e / KB;
+            L.pan[i * KB + e % KB] = (int32_t)sym((double)L.pan[i * KB + e % KB], mod);
         }
         __syncthreads();
         // trailing update of rows s+kbe .., columns c0 ..: each thread owns a
@@ -214,8 +220,9 @@ __device__ int blocked_lu(T *A, int64_t lda, int m, int n, int r_known, const Mo
                                 const int32_t *lrow = &L.pan[(kbe + i) * KB];
 #pragma unroll
                                 for (int t = 0; t < KB; ++t)
-                                    if (t < kbe) acc = fma(-sym((double)lrow[t], mod), u[t], acc);
-                                const double x = mod_reduce(acc, mod);
+                                    if (t < kbe) acc = fma(-(double)lrow[t], u[t], acc);
+                                double x = sym_reduce(acc, mod);
+                                x = x < 0.0 ? x + mod.p : x;   // canonical
                                 A[(int64_t)(s + kbe + i) * lda + c0 + c] = from_f64<T>(x);
                                 if (kbe < kb) nz |= (x != 0.0);
                             }
