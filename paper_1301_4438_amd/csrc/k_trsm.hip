@@ -143,8 +143,9 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t
 // The 64 x 64 operand blocks (L'_qj, then W'_q) form one sequence of jobs:
 // each is read from memory with whole-row loads (coalesced in both
 // orientations), converted once to negated symmetric residues and stored in
-// one of two LDS buffers; the next job's loads are issued before the current
-// job's matrix-core operations, so memory latency hides behind them.  One
+// one of two LDS buffers; the loads of the job after next are issued before
+// the current job's matrix-core operations, so memory latency hides behind
+// two jobs.  One
 // barrier per job: a buffer is rewritten two jobs after it was read, and
 // every thread has passed the previous job's barrier by then.  Four
 // accumulators take turns, so consecutive matrix-core operations are
@@ -241,13 +242,13 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt
         }
     };
     // Jobs run as one flat sequence (q, j) = (0, 0), (1, 0), (1, 1), (2, 0),
-    // ...; two register sets alternate (the loop is unrolled by two), so the
-    // loads of job n + 1 are issued before job n is stored and have a whole
-    // job's time to arrive.
-    T ra[16], rb[16];
+    // ...; three register sets rotate (the loop is unrolled by three), so the
+    // loads of job n + 2 are issued before job n is stored and have two whole
+    // jobs' time to arrive (one job is shorter than a load from memory).
+    T ra[16], rb[16], rc[16];
     v4d x[4];
     int buf = 0, kacc = 0;
-    auto do_job = [&](int q, int j, T (&cur)[16], T (&nxt)[16]) {
+    auto do_job = [&](int q, int j, T (&cur)[16], T (&nxt)[16], int q2, int j2) {
         const int i0 = 64 * q;
         if (j == 0) {
 #pragma unroll
@@ -261,8 +262,7 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt
             if (q + 1 < nb) load_b(q + 1);
             kacc = 0;
         }
-        if (j < q) load_job(q, j + 1, nxt);
-        else if (q + 1 < nb) load_job(q + 1, 0, nxt);
+        if (q2 < nb) load_job(q2, j2, nxt);
         store_job(q, j, buf, cur);
         if (j == q) {
             // acc = B'_q - sum L' X, reduced: the W job's right operand
@@ -295,19 +295,32 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt
             }
         }
     };
-    load_b(0);
-    load_job(0, 0, ra);
-    int q = 0, j = 0;
-    auto advance = [&]() {
+    auto next = [](int &q, int &j) {
         if (j < q) ++j;
         else { ++q; j = 0; }
     };
+    // jobs n, n + 1 and n + 2 (the one whose loads job n issues)
+    int q = 0, j = 0, q1 = 0, j1 = 0;
+    next(q1, j1);
+    int q2 = q1, j2 = j1;
+    next(q2, j2);
+    load_b(0);
+    load_job(0, 0, ra);
+    if (q1 < nb) load_job(q1, j1, rb);
+    auto shift = [&]() {
+        q = q1; j = j1;
+        q1 = q2; j1 = j2;
+        next(q2, j2);
+    };
     while (q < nb) {
-        do_job(q, j, ra, rb);
-        advance();
+        do_job(q, j, ra, rc, q2, j2);
+        shift();
         if (q >= nb) break;
-        do_job(q, j, rb, ra);
-        advance();
+        do_job(q, j, rb, ra, q2, j2);
+        shift();
+        if (q >= nb) break;
+        do_job(q, j, rc, rb, q2, j2);
+        shift();
     }
 }
 
