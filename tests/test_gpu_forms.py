@@ -29,9 +29,12 @@ def note(*a):
 
 
 # Shapes span several 128 x 128 tiles, ragged edges, inner dimensions that are
-# not multiples of 64 and (last two) more than one 4096-deep piece.
+# not multiples of 64, padded depths of 64 + 128 j (a last half step when 128
+# inner positions are staged per step) and 128 j, and (last two) more than
+# one 4096-deep piece.
 I8_SHAPES = [(1, 1, 1), (15, 17, 16), (64, 64, 64), (65, 129, 100), (128, 128, 128), (129, 127, 300),
-             (200, 333, 64), (300, 300, 700), (257, 130, 1), (70, 90, 4097), (33, 200, 9000)]
+             (200, 333, 64), (300, 300, 700), (257, 130, 1), (129, 131, 150), (131, 129, 250),
+             (70, 90, 4097), (33, 200, 9000)]
 
 
 def _extremes(p, shape, g):
