@@ -132,12 +132,11 @@ size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p,
  * exact recursion runs from the start.  The result is the same either way;
  * only the time differs (faster on generic inputs, about one extra partial
  * attempt otherwise).
- *   stream   HIP stream the work is ordered on (NULL: the null stream).  The
- *            call returns when the decomposition is complete.  Part of the
- *            work (the two independent triangular solves of each recursion
- *            node) runs on an auxiliary stream of the calling thread, forked
- *            from and joined back into `stream` with events; that stream is
- *            created on the first call of each thread and device.
+ *   stream   HIP stream all the work is ordered on (NULL: the null
+ *            stream).  The call returns when the decomposition is complete.
+ *            The two independent triangular solves of each recursion node
+ *            share their launches (one grid carries both), so no other
+ *            stream is used.
  * m == 0 or n == 0 gives r = 0 and identity permutations.
  * Errors: PLUQ_ERR_ARG, PLUQ_ERR_MODULUS, PLUQ_ERR_UNSUPPORTED,
  * PLUQ_ERR_WORKSPACE (all before A is touched), PLUQ_ERR_RANGE (validation

@@ -96,42 +96,6 @@ bool ensure_pinned(size_t idx_elems, size_t pq_elems) {
     return true;
 }
 
-// Auxiliary stream of the calling thread on its current device (default
-// priority), with the two events that fork work to it and join it back;
-// created on first use and kept until the thread ends.  Null if it cannot be
-// created: the decomposition then runs on the caller's stream alone.
-struct AuxStream {
-    int dev = -1;
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    void release() {
-        if (s) (void)hipStreamDestroy(s);
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-        s = nullptr;
-        fork = join = nullptr;
-        dev = -1;
-    }
-    ~AuxStream() { release(); }
-};
-thread_local AuxStream g_aux;
-
-AuxStream *aux_stream() {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    if (g_aux.s && g_aux.dev == dev) return &g_aux;
-    g_aux.release();
-    if (hipStreamCreateWithFlags(&g_aux.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&g_aux.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&g_aux.join, hipEventDisableTiming) != hipSuccess) {
-        g_aux.release();
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    g_aux.dev = dev;
-    return &g_aux;
-}
-
 std::once_flag g_bc_once;
 int g_bc_cap = 0;
 
@@ -168,7 +132,7 @@ Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec)
     L.tab_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
     L.w_bytes = trsm_w_bytes(std::min(m, n), esz);
     L.w_off = L.tab_off + align_up(L.tab_bytes);
-    L.w2_off = L.w_off + align_up(L.w_bytes);   // second solve, on the auxiliary stream
+    L.w2_off = L.w_off + align_up(L.w_bytes);   // the upper solve of a node's pair
     L.scratch_off = L.w2_off + align_up(L.w_bytes);
     L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0) ? limb_bytes_for(m, n, p) : 0;
     L.limb_off = L.scratch_off + align_up(L.scratch_bytes);
@@ -265,11 +229,6 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.scratch_bytes = L.scratch_bytes;
         c.trsm_w = w + L.w_off;
         c.trsm_w2 = w + L.w2_off;
-        if (AuxStream *ax = aux_stream()) {
-            c.aux = ax->s;
-            c.ev_fork = ax->fork;
-            c.ev_join = ax->join;
-        }
         if (L.limb_bytes) {
             c.limb = w + L.limb_off;
             c.limb_bytes = L.limb_bytes;

@@ -351,6 +351,48 @@ void Ctx::trsm_run_rec(char *B, int64_t ldb, int64_t nrows, const char *U, int64
     trsm_run_rec(B + (size_t)r1 * esz, ldb, nrows, U + ((size_t)r1 * ldu + r1) * esz, ldu, r - r1, off + r1);
 }
 
+// The two solves of a node, D <- L^{-1} D (r x ncols at (di, dj)) and
+// E <- E U^{-1} (nrows x r at (ei, ej)), with L\U the r x r block at
+// (ti, tj): they read and write disjoint blocks and recurse at the same
+// split points, so each launch carries both, the diagonal inverses, every
+// leaf and every MM update (two problems), on the one stream.
+void Ctx::trsm_pair(int64_t ti, int64_t tj, int64_t r, int64_t di, int64_t dj, int64_t ncols, int64_t ei, int64_t ej,
+                    int64_t nrows) {
+    if (r <= 0) return;
+    if (ncols <= 0 || nrows <= 0) {
+        if (ncols > 0) trsm_llu(ti, tj, r, di, dj, ncols);
+        if (nrows > 0) trsm_run(ei, ej, nrows, ti, tj, r);
+        return;
+    }
+    const char *T = at(ti, tj);
+    launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 4, [&] {
+        return launch_trsm_diag_inv_pair(dt, T, lda, T, lda, r, trsm_w, trsm_w2, (double)p, kchunk, st);
+    });
+    trsm_pair_rec(T, r, at(di, dj), at(ei, ej), ncols, nrows, 0);
+}
+
+void Ctx::trsm_pair_rec(const char *T, int64_t r, char *BD, char *BE, int64_t ncols, int64_t nrows, int64_t off) {
+    if (r <= TRSM_FUSE_MAX) {
+        const size_t wo = (size_t)(off / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
+        const double nst = (double)(ncols + nrows);
+        launch(K_TRSM, (double)r * r * nst + 2.0 * TRSM_NB * r * nst, (r * r + 2.0 * r * nst) * esz, [&] {
+            return launch_trsm_leaf_pair(dt, T, lda, T, lda, r, BD, lda, ncols, BE, lda, nrows, trsm_w + wo,
+                                         trsm_w2 + wo, (double)p, kchunk, st);
+        });
+        return;
+    }
+    const int64_t r1 = trsm_split(r);
+    trsm_pair_rec(T, r1, BD, BE, ncols, nrows, off);
+    MMProblem pb[2];
+    pb[0] = mmprob(BD + (size_t)r1 * lda * esz, lda, r - r1, ncols);   // D2 -= L21 X1
+    mmpair(pb[0], 0, T + (size_t)r1 * lda * esz, lda, BD, lda, r1);
+    pb[1] = mmprob(BE + (size_t)r1 * esz, lda, nrows, r - r1);         // E2 -= Y1 U12
+    mmpair(pb[1], 0, BE, lda, T + (size_t)r1 * esz, lda, r1);
+    mm(pb, 2);
+    trsm_pair_rec(T + ((size_t)r1 * lda + r1) * esz, r - r1, BD + (size_t)r1 * lda * esz, BE + (size_t)r1 * esz,
+                  ncols, nrows, off + r1);
+}
+
 void Ctx::trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols) {
     trsm_llu_p(at(li, lj), lda, r, at(bi, bj), lda, ncols);
 }
@@ -560,21 +602,8 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
     Zero zFGH[3] = {Z_UNKNOWN, Z_UNKNOWN, Z_UNKNOWN};
     int32_t gFGH[3] = {0, 0, 0};
     if (r1 > 0) {
-        // D <- L1^{-1} B1 and E <- C1 U1^{-1} read and write disjoint blocks:
-        // E is solved on the auxiliary stream while D is solved here
-        const bool fork = aux && n - h > 0 && m - k > 0;
-        if (fork) {
-            check(hipEventRecord(ev_fork, st));
-            check(hipStreamWaitEvent(aux, ev_fork, 0));
-            on_aux([&] { trsm_run(gi + k, gj, m - k, gi, gj, r1); });
-        }
-        trsm_llu(gi, gj, r1, gi, gj + h, n - h);       // D <- L1^{-1} B1
-        if (fork) {
-            check(hipEventRecord(ev_join, aux));
-            check(hipStreamWaitEvent(st, ev_join, 0));
-        } else {
-            trsm_run(gi + k, gj, m - k, gi, gj, r1);   // E <- C1 U1^{-1}
-        }
+        // D <- L1^{-1} B1 and E <- C1 U1^{-1}: independent, solved together
+        trsm_pair(gi, gj, r1, gi, gj + h, n - h, gi + k, gj, m - k);
         MMProblem pb[3];
         pb[0] = mmprob(at(bF.i, bF.j), lda, bF.m, bF.n);
         mmpair(pb[0], 0, at(gi + r1, gj), lda, at(gi, gj + h), lda, r1);

@@ -83,10 +83,8 @@ struct Ctx {
     size_t idx_cap = 0, idx_used = 0;
     int32_t *d_stat = nullptr;
     uint16_t *inv_table = nullptr;   // inverses mod p for the base case (or null)
-    char *trsm_w = nullptr;          // I - T_qq^{-1} blocks of the current solve
-    char *trsm_w2 = nullptr;         // the same for a solve on the auxiliary stream
-    hipStream_t aux = nullptr;       // auxiliary stream (independent solves), or null
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    char *trsm_w = nullptr;          // I - T_qq^{-1} blocks of the current (or lower) solve
+    char *trsm_w2 = nullptr;         // the same for the upper solve of a node's pair
     char *limb = nullptr;            // digit planes of the INT8-limb form (or null)
     size_t limb_bytes = 0;
     int kchunk32 = 0;                // FP32 form: products between reductions
@@ -126,18 +124,9 @@ struct Ctx {
     void perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
     void mm(MMProblem *probs, int n);
     bool mm_i8(const MMProblem &pb);
-    // Run f with the auxiliary stream and workspace as the current ones (the
-    // INT8 digit planes are not shared: updates issued there use FP64).
-    template <class F> void on_aux(F f) {
-        std::swap(st, aux);
-        std::swap(trsm_w, trsm_w2);
-        char *lb = limb;
-        limb = nullptr;
-        f();
-        limb = lb;
-        std::swap(trsm_w, trsm_w2);
-        std::swap(st, aux);
-    }
+    void trsm_pair(int64_t ti, int64_t tj, int64_t r, int64_t di, int64_t dj, int64_t ncols, int64_t ei, int64_t ej,
+                   int64_t nrows);
+    void trsm_pair_rec(const char *T, int64_t r, char *BD, char *BE, int64_t ncols, int64_t nrows, int64_t off);
     void trsm_llu(int64_t li, int64_t lj, int64_t r, int64_t bi, int64_t bj, int64_t ncols);
     void trsm_run(int64_t bi, int64_t bj, int64_t nrows, int64_t ui, int64_t uj, int64_t r);
     void trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols);

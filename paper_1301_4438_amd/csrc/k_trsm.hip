@@ -26,14 +26,24 @@ namespace pluq {
 // Products are of symmetric residues, reduced (symmetric reduction) after
 // every 16 terms; the sums run as two independent chains and the blocks of
 // one distance together, since the kernel is bound by dependent latency.
+struct DiagSmem {
+    double Ls[64][65];   // strict lower part (symmetric residues)
+    double Xs[64][65];   // the inverse being built (symmetric)
+    double Ts[3][16][17];
+    double dinv[64];
+};
+
+// Work-group body for diagonal block `blk`; the LDS comes from the caller so
+// that one kernel can hold the lower and the upper case.
 template <typename T, bool UPPER>
-__global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t ldt, int r, T *W, ModP mod) {
-    __shared__ double Ls[64][65];   // strict lower part (symmetric residues)
-    __shared__ double Xs[64][65];   // the inverse being built (symmetric)
-    __shared__ double Ts[3][16][17];
-    __shared__ double dinv[64];
+__device__ __forceinline__ void diag_inv_body(const T *Tm, int64_t ldt, int r, T *W, ModP mod, int blk,
+                                              DiagSmem &sm) {
+    auto &Ls = sm.Ls;
+    auto &Xs = sm.Xs;
+    auto &Ts = sm.Ts;
+    auto &dinv = sm.dinv;
     const int tid = threadIdx.x;
-    const int o = blockIdx.x * 64;
+    const int o = blk * 64;
     const int nb = min(64, r - o);
     const T *Tq = Tm + (int64_t)o * ldt + o;
     {
@@ -120,13 +130,30 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t
         for (int b = 0; b < 4 - d; ++b) Xs[16 * (b + d) + a][16 * b + c] = sym_reduce(-acc[b], mod);
         __syncthreads();
     }
-    T *Wq = W + (int64_t)blockIdx.x * 64 * 64;
+    T *Wq = W + (int64_t)blk * 64 * 64;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int e = tid + 256 * q, i = e >> 6, j = e & 63;
         const double x = UPPER ? Xs[j][i] : Xs[i][j];
         Wq[e] = from_f64<T>(mod_reduce((i == j ? 1.0 : 0.0) - x, mod));
     }
+}
+
+template <typename T, bool UPPER>
+__global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t ldt, int r, T *W, ModP mod) {
+    __shared__ DiagSmem sm;
+    diag_inv_body<T, UPPER>(Tm, ldt, r, W, mod, blockIdx.x, sm);
+}
+
+// The diagonal blocks of a lower and an upper triangle of the same order in
+// one launch (the two solves of a recursion node): work-groups [0, nb) take
+// the lower one, [nb, 2 nb) the upper one.
+template <typename T>
+__global__ __launch_bounds__(256) void trsm_diag_inv_pair_kernel(const T *Lm, int64_t ldl, const T *Um, int64_t ldu,
+                                                                 int r, T *WL, T *WU, ModP mod, int nb) {
+    __shared__ DiagSmem sm;
+    if ((int)blockIdx.x < nb) diag_inv_body<T, false>(Lm, ldl, r, WL, mod, blockIdx.x, sm);
+    else diag_inv_body<T, true>(Um, ldu, r, WU, mod, blockIdx.x - nb, sm);
 }
 
 // Leaf solve of order r <= TRSM_FUSE_MAX.  The lower case solves L X = B
@@ -156,15 +183,22 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_kernel(const T *Tm, int64_t
 // there), right-hand sides past nst are computed on zeros and not stored.
 constexpr int TRSM_STRIP = 16;
 
+struct LeafSmem {
+    double Xs[TRSM_FUSE_MAX][TRSM_STRIP + 1];   // solved strip (symmetric)
+    double Acc[64][TRSM_STRIP + 1];              // B'_q - sum L' X (symmetric)
+    double Ls[2][64][65];                        // operand blocks (negated symmetric)
+};
+
+// Work-group body for strip `blk`; the LDS comes from the caller.
 template <typename T, bool UPPER, bool RED16>
-__global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt, int r, T *B, int64_t ldb,
-                                                        int nst, const T *W, ModP mod, int kchunk) {
+__device__ __forceinline__ void trsm_leaf_body(const T *Tm, int64_t ldt, int r, T *B, int64_t ldb, int nst,
+                                               const T *W, ModP mod, int kchunk, int blk, LeafSmem &sm) {
     typedef double v4d __attribute__((ext_vector_type(4)));
-    __shared__ double Xs[TRSM_FUSE_MAX][TRSM_STRIP + 1];   // solved strip (symmetric)
-    __shared__ double Acc[64][TRSM_STRIP + 1];              // B'_q - sum L' X (symmetric)
-    __shared__ double Ls[2][64][65];                        // operand blocks (negated symmetric)
+    auto &Xs = sm.Xs;
+    auto &Acc = sm.Acc;
+    auto &Ls = sm.Ls;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int c0 = blockIdx.x * TRSM_STRIP;
+    const int c0 = blk * TRSM_STRIP;
     const int col = lane & 15;                 // right-hand side within the strip
     const int kl = lane >> 4;                  // k offset of this lane's operand
     const int nb = (r + 63) / 64;
@@ -324,6 +358,29 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt
     }
 }
 
+template <typename T, bool UPPER, bool RED16>
+__global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt, int r, T *B, int64_t ldb,
+                                                        int nst, const T *W, ModP mod, int kchunk) {
+    __shared__ LeafSmem sm;
+    trsm_leaf_body<T, UPPER, RED16>(Tm, ldt, r, B, ldb, nst, W, mod, kchunk, blockIdx.x, sm);
+}
+
+// The two leaf solves of a recursion node in one launch, L X = BD (lower,
+// ncols right-hand sides) and X U = BE (upper, nrows right-hand sides), with
+// triangles of the same order: work-groups [0, gD) take strips of BD, the
+// rest strips of BE.
+template <typename T, bool RED16>
+__global__ __launch_bounds__(256) void trsm_leaf_pair_kernel(const T *Lm, int64_t ldl, const T *Um, int64_t ldu, int r,
+                                                             T *BD, int64_t ldbd, int ncols, T *BE, int64_t ldbe,
+                                                             int nrows, const T *WL, const T *WU, ModP mod, int kchunk,
+                                                             int gD) {
+    __shared__ LeafSmem sm;
+    if ((int)blockIdx.x < gD)
+        trsm_leaf_body<T, false, RED16>(Lm, ldl, r, BD, ldbd, ncols, WL, mod, kchunk, blockIdx.x, sm);
+    else
+        trsm_leaf_body<T, true, RED16>(Um, ldu, r, BE, ldbe, nrows, WU, mod, kchunk, blockIdx.x - gD, sm);
+}
+
 static ModP make_mod(double p) {
     ModP m;
     m.p = p;
@@ -371,6 +428,62 @@ static hipError_t leaf_t(int side, const void *Tm, int64_t ldt, int r, void *B, 
     }
 #undef PLUQ_LEAF
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t diag_inv_pair_t(const void *Lm, int64_t ldl, const void *Um, int64_t ldu, int r, void *WL, void *WU,
+                                  double p, hipStream_t st) {
+    const int nb = (int)cdiv64(r, 64);
+    PLUQ_LAUNCH((trsm_diag_inv_pair_kernel<T>), dim3((unsigned)(2 * nb)), dim3(256), 0, st, (const T *)Lm, ldl,
+                (const T *)Um, ldu, r, (T *)WL, (T *)WU, make_mod(p), nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_diag_inv_pair(int dtype, const void *Lm, int64_t ldl, const void *Um, int64_t ldu, int64_t r,
+                                     void *WL, void *WU, double p, int kchunk, hipStream_t st) {
+    if (r <= 0) return hipSuccess;
+    if (kchunk < 1 || r > INT32_MAX / 2) return hipErrorInvalidValue;
+    switch (dtype) {
+    case DT_I64: return diag_inv_pair_t<int64_t>(Lm, ldl, Um, ldu, (int)r, WL, WU, p, st);
+    case DT_F64: return diag_inv_pair_t<double>(Lm, ldl, Um, ldu, (int)r, WL, WU, p, st);
+    case DT_I32: return diag_inv_pair_t<int32_t>(Lm, ldl, Um, ldu, (int)r, WL, WU, p, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t leaf_pair_t(const void *Lm, int64_t ldl, const void *Um, int64_t ldu, int r, void *BD, int64_t ldbd,
+                              int ncols, void *BE, int64_t ldbe, int nrows, const void *WL, const void *WU, double p,
+                              int kchunk, hipStream_t st) {
+    const int gD = (int)cdiv64(ncols, TRSM_STRIP), gE = (int)cdiv64(nrows, TRSM_STRIP);
+    const ModP md = make_mod(p);
+#define PLUQ_LEAF_PAIR(R16)                                                                                     \
+    PLUQ_LAUNCH((trsm_leaf_pair_kernel<T, R16>), dim3((unsigned)(gD + gE)), dim3(256), 0, st, (const T *)Lm, ldl, \
+                (const T *)Um, ldu, r, (T *)BD, ldbd, ncols, (T *)BE, ldbe, nrows, (const T *)WL, (const T *)WU, md, \
+                kchunk, gD)
+    if (kchunk < 64) PLUQ_LEAF_PAIR(true);
+    else PLUQ_LEAF_PAIR(false);
+#undef PLUQ_LEAF_PAIR
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm_leaf_pair(int dtype, const void *Lm, int64_t ldl, const void *Um, int64_t ldu, int64_t r,
+                                 void *BD, int64_t ldbd, int64_t ncols, void *BE, int64_t ldbe, int64_t nrows,
+                                 const void *WL, const void *WU, double p, int kchunk, hipStream_t st) {
+    if (r <= 0 || ncols <= 0 || nrows <= 0) return hipErrorInvalidValue;
+    if (r > TRSM_FUSE_MAX || kchunk < 16 || ncols > INT32_MAX / 2 || nrows > INT32_MAX / 2) return hipErrorInvalidValue;
+    switch (dtype) {
+    case DT_I64:
+        return leaf_pair_t<int64_t>(Lm, ldl, Um, ldu, (int)r, BD, ldbd, (int)ncols, BE, ldbe, (int)nrows, WL, WU, p,
+                                    kchunk, st);
+    case DT_F64:
+        return leaf_pair_t<double>(Lm, ldl, Um, ldu, (int)r, BD, ldbd, (int)ncols, BE, ldbe, (int)nrows, WL, WU, p,
+                                   kchunk, st);
+    case DT_I32:
+        return leaf_pair_t<int32_t>(Lm, ldl, Um, ldu, (int)r, BD, ldbd, (int)ncols, BE, ldbe, (int)nrows, WL, WU, p,
+                                    kchunk, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_trsm_leaf(int dtype, int side, const void *Tm, int64_t ldt, int64_t r, void *B, int64_t ldb,

@@ -98,6 +98,16 @@ constexpr int TRSM_FUSE_MAX = 256;
 hipError_t launch_trsm_leaf(int dtype, int side, const void *T, int64_t ldt, int64_t r, void *B, int64_t ldb,
                             int64_t nst, const void *W, double p, int kchunk, hipStream_t st);
 
+// The two solves of a recursion node together, on triangles of the same
+// order r: the diagonal blocks of L (unit lower, into WL) and U (upper, into
+// WU) in one launch, and the leaves BD (r x ncols) <- L^{-1} BD and
+// BE (nrows x r) <- BE U^{-1} in one launch (ncols, nrows > 0).
+hipError_t launch_trsm_diag_inv_pair(int dtype, const void *L, int64_t ldl, const void *U, int64_t ldu, int64_t r,
+                                     void *WL, void *WU, double p, int kchunk, hipStream_t st);
+hipError_t launch_trsm_leaf_pair(int dtype, const void *L, int64_t ldl, const void *U, int64_t ldu, int64_t r,
+                                 void *BD, int64_t ldbd, int64_t ncols, void *BE, int64_t ldbe, int64_t nrows,
+                                 const void *WL, const void *WU, double p, int kchunk, hipStream_t st);
+
 // dst[i][j] = src[rmap ? rmap[i] : i][cmap ? cmap[j] : j], rows x cols.
 hipError_t launch_gather2d(int dtype, const void *src, int64_t lds, void *dst, int64_t ldd,
                            int64_t rows, int64_t cols, const int32_t *rmap,
