@@ -64,6 +64,7 @@ struct Pinned {
     int32_t *idx = nullptr;
     size_t idx_cap = 0;
     int32_t *stat = nullptr;
+    int32_t *stat_dev = nullptr;   // the device's address of `stat`, or null
     int64_t *pq = nullptr;
     size_t pq_cap = 0;
 };
@@ -76,6 +77,12 @@ bool ensure_pinned(size_t idx_elems, size_t pq_elems) {
             g_pin.stat = nullptr;
             return false;
         }
+        // The status words are written by the kernels straight into this
+        // (coherent) host memory when the device can address it, so that a
+        // read-back is a stream synchronisation with no copy launched.
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, g_pin.stat, 0) == hipSuccess) g_pin.stat_dev = (int32_t *)dp;
+        else (void)hipGetLastError();
     }
     if (g_pin.idx_cap < idx_elems) {
         if (g_pin.idx) (void)hipHostFree(g_pin.idx);
@@ -223,6 +230,10 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.st = (hipStream_t)stream;
         char *w = (char *)dWork;
         c.d_stat = (int32_t *)(w + L.stat_off);
+        if (g_pin.stat_dev) {
+            c.d_stat = g_pin.stat_dev;
+            c.stat_mapped = true;
+        }
         c.d_idx = (int32_t *)(w + L.idx_off);
         c.idx_cap = L.idx_elems;
         c.scratch = w + L.scratch_off;
@@ -262,7 +273,9 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             // the sticky flags start cleared
             c.h_stat[STAT_SPEC] = 0;
             c.h_stat[STAT_ERR] = 0;
-            c.check(hipMemcpyAsync(c.d_stat + STAT_SPEC, c.h_stat + STAT_SPEC, 2 * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+            if (!c.stat_mapped)
+                c.check(hipMemcpyAsync(c.d_stat + STAT_SPEC, c.h_stat + STAT_SPEC, 2 * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, c.st));
             bool done = false;
             if (L.spec_bytes && (m > c.cap || n > c.cap)) {
                 char *backup = w + L.spec_off;

@@ -119,15 +119,21 @@ const int32_t *Ctx::upload(const int32_t *v, int64_t n) {
     return d;
 }
 
+// Flag generations never repeat within a thread (the status words it uses
+// outlive a call), so a flag left by an earlier call cannot match.
+thread_local int32_t g_gen = 0;
+
 int32_t Ctx::next_gen() {
-    gen = (gen % 2000000000) + 1;
-    return gen;
+    g_gen = (g_gen % 2000000000) + 1;
+    return g_gen;
 }
 
-// Read `count` int32 status words back (synchronising).
+// Read `count` int32 status words back (synchronising).  When the kernels
+// write them into mapped host memory the synchronisation alone suffices.
 void Ctx::read_status(int64_t offset, int64_t count) {
-    check(hipMemcpyAsync(h_stat + offset, d_stat + offset, (size_t)count * sizeof(int32_t),
-                         hipMemcpyDeviceToHost, st));
+    if (!stat_mapped)
+        check(hipMemcpyAsync(h_stat + offset, d_stat + offset, (size_t)count * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st));
     sync();
 }
 

@@ -91,7 +91,7 @@ struct Ctx {
     // pinned host mirrors
     int32_t *h_idx = nullptr;
     int32_t *h_stat = nullptr;
-    int32_t gen = 0;
+    bool stat_mapped = false;        // d_stat is h_stat's device address (no copies)
     Stats stats;
     // Speculative mode: every base-case tile is taken to be full rank in the
     // identity order without reading its result back; the tiles record a
