@@ -283,7 +283,9 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
                 c.launch(K_PERM, 0, bytes, [&] { return launch_gather2d(c.dt, dA, lda, backup, n, m, n, nullptr, nullptr, c.st); });
                 c.spec = true;
                 try {
-                    r = c.node(0, 0, m, n, Z_UNKNOWN, prow, pcol);
+                    // nor is A itself tested for zero first: an all-zero A
+                    // fails its first tile and goes to the exact recursion
+                    r = c.node(0, 0, m, n, Z_NONZERO, prow, pcol);
                     c.check_spec();
                     done = true;
                 } catch (const SpecFail &) {

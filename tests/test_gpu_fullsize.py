@@ -182,9 +182,10 @@ def test_concurrent_streams_vs_oracle(gpu_lib):
 
 def test_speculation_on_off_identical(gpu_lib):
     """The speculative first attempt (every base-case tile full rank in the
-    identity order) and the exact recursion give the same result on generic
-    inputs (where the attempt succeeds) and on inputs whose rank profile is
-    not generic (where it fails part-way and the matrix is restored and
+    identity order, and A itself not tested for zero) and the exact
+    recursion give the same result on generic inputs (where the attempt
+    succeeds) and on inputs whose rank profile is not generic, the zero
+    matrix included (where it fails part-way and the matrix is restored and
     decomposed again); both equal the oracle."""
     import torch
     p = 65521
@@ -192,7 +193,8 @@ def test_speculation_on_off_identical(gpu_lib):
              ("xy", gen.xy_permuted(640, 700, 300, p, 22)),
              ("planted", gen.planted_leu(600, 600, 400, p, 23)[0]),
              ("zero_block", gen.zero_block(512, 768, 300, 100, p, 24)),
-             ("rank_one_tile", (gen.uniform(384, 1, p, 25) * gen.uniform(1, 384, p, 26)) % p)]
+             ("rank_one_tile", (gen.uniform(384, 1, p, 25) * gen.uniform(1, 384, p, 26)) % p),
+             ("all_zero", np.zeros((600, 520), np.int64))]
     for name, A in cases:
         note("speculation", name, A.shape)
         Ad = torch.from_numpy(np.ascontiguousarray(A)).to(torch.float64).cuda()
