@@ -88,7 +88,7 @@ def rpm(A, p: int):
     rc = np.full(max(m, 1), -1, dtype=np.int64)
     r = lib().oracle_rpm(m, n, _p(W), p, _p(rc))
     if r < 0:
-        raise OracleError("oracle_rpm: out of memory")
+        raise OracleError("oracle_rpm failed (allocation, or p outside [2, 2^32))")
     return int(r), rc[:m]
 
 

@@ -9,8 +9,8 @@
  * shares no code with the GPU path.
  *
  * All matrices are row-major int64 with entries in [0, p); every product is
- * reduced immediately with the C `%` operator on unsigned 64-bit integers,
- * so p must satisfy (p-1)^2 < 2^64.
+ * reduced immediately with the C `%` operator on unsigned integers, so p must
+ * be below 2^32 (p^2 + p then fits an unsigned 64-bit integer).
  *
  * The output convention ("PLUQ-Z") is the one computed by the paper's
  * Algorithm 1 (Section 2) with floor(m/2) x floor(n/2) splits and with the
@@ -51,6 +51,9 @@ typedef unsigned __int128 u128;
 static inline uint64_t fadd(uint64_t a, uint64_t b, uint64_t p) { return (a + b) % p; }
 static inline uint64_t fsub(uint64_t a, uint64_t b, uint64_t p) { return (a + p - b) % p; }
 static inline uint64_t fmul(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)(((u128)a * b) % p); }
+/* c - a b mod p for a, b, c in [0, p), p < 2^32: c + p^2 - a b lies in
+ * (0, p^2 + p) and is reduced by one `%` (the elimination's update). */
+static inline uint64_t fmsub(uint64_t c, uint64_t a, uint64_t b, uint64_t p) { return (c + p * p - a * b) % p; }
 
 /* Inverse by the extended Euclidean algorithm; a must be non-zero mod p. */
 uint64_t oracle_inv(uint64_t a, uint64_t p)
@@ -131,10 +134,11 @@ static void rot_cols(int64_t *A, int64_t m, int64_t n, int64_t lo, int64_t hi)
  *     rank-profile property).
  * Only the rank profile matrix is kept from this stage: rpm_col[i] is the
  * column of the pivot of original row i, or -1.  Returns r, or -1 on
- * allocation failure.  A is m x n row-major (ld = n), overwritten.
+ * allocation failure or a modulus outside [2, 2^32).  A is m x n row-major (ld = n), overwritten.
  */
 int64_t oracle_rpm(int64_t m, int64_t n, int64_t *A, uint64_t p, int64_t *rpm_col)
 {
+    if (p < 2 || p >= ((uint64_t)1 << 32)) return -1;
     int64_t *P = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
     int64_t *Q = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
     if (!P || !Q) { free(P); free(Q); return -1; }
@@ -181,7 +185,7 @@ int64_t oracle_rpm(int64_t m, int64_t n, int64_t *A, uint64_t p, int64_t *rpm_co
             rowk[qc] = (int64_t)l;
             if (l == 0) continue;
             for (int64_t c = qc + 1; c < n; ++c)
-                rowk[c] = (int64_t)fsub((uint64_t)rowk[c], fmul(l, (uint64_t)prow[c], p), p);
+                rowk[c] = (int64_t)fmsub((uint64_t)rowk[c], l, (uint64_t)prow[c], p);
         }
         if (rot_rows(A, n, r, pr) != ORC_OK) { free(P); free(Q); return -1; }
         rot_cols(A, m, n, r, qc);
@@ -326,6 +330,7 @@ done:
 int oracle_ordered_lu(int64_t m, int64_t n, const int64_t *A, uint64_t p, int64_t r,
                       const int64_t *P, const int64_t *Q, int64_t *X)
 {
+    if (p < 2 || p >= ((uint64_t)1 << 32)) return ORC_ERR_ARG;
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < n; ++j)
@@ -342,7 +347,7 @@ int oracle_ordered_lu(int64_t m, int64_t n, const int64_t *A, uint64_t p, int64_
             row[s] = (int64_t)l;
             if (l == 0) continue;
             for (int64_t j = s + 1; j < n; ++j)
-                row[j] = (int64_t)fsub((uint64_t)row[j], fmul(l, (uint64_t)urow[j], p), p);
+                row[j] = (int64_t)fmsub((uint64_t)row[j], l, (uint64_t)urow[j], p);
         }
     }
     for (int64_t i = r; i < m; ++i)
@@ -358,7 +363,7 @@ int oracle_ordered_lu(int64_t m, int64_t n, const int64_t *A, uint64_t p, int64_
 int oracle_pluqz(int64_t m, int64_t n, const int64_t *A, uint64_t p,
                  int64_t *P, int64_t *Q, int64_t *X, int64_t *r_out)
 {
-    if (m < 0 || n < 0 || p < 2) return ORC_ERR_ARG;
+    if (m < 0 || n < 0 || p < 2 || p >= ((uint64_t)1 << 32)) return ORC_ERR_ARG;
     *r_out = 0;
     for (int64_t t = 0; t < m; ++t) P[t] = t;
     for (int64_t t = 0; t < n; ++t) Q[t] = t;
