@@ -92,7 +92,6 @@ typedef struct {
     int32_t form;             /* pluq_form */
     int32_t validate_entries; /* non-zero: scan A for entries outside [0,p) first */
     int32_t cutoff_override;  /* > 0: base-case tiles at most this many rows and columns (tuning only) */
-    int32_t trsm_leaf_override; /* reserved: accepted in [0, 64], no effect */
     int32_t batch_panel;        /* batched form: panel width 8 or 16 (0: 8; tuning only) */
     int32_t batch_groups;       /* batched form: persistent work-groups per compute unit
                                    (0: 4 for panel 8, 2 for panel 16; tuning only) */

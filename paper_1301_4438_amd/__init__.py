@@ -40,7 +40,7 @@ class PluqError(RuntimeError):
 
 class pluq_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("validate_entries", ctypes.c_int32),
-                ("cutoff_override", ctypes.c_int32), ("trsm_leaf_override", ctypes.c_int32),
+                ("cutoff_override", ctypes.c_int32),
                 ("batch_panel", ctypes.c_int32), ("batch_groups", ctypes.c_int32),
                 ("no_speculation", ctypes.c_int32)]
 
@@ -131,13 +131,12 @@ def _stream(t):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _opts(form="fp64", validate=False, cutoff=0, trsm_leaf=0, batch_panel=0, batch_groups=0, speculate=True):
+def _opts(form="fp64", validate=False, cutoff=0, batch_panel=0, batch_groups=0, speculate=True):
     o = pluq_opts()
     o.no_speculation = 0 if speculate else 1
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.validate_entries = int(bool(validate))
     o.cutoff_override = int(cutoff)
-    o.trsm_leaf_override = int(trsm_leaf)
     o.batch_panel = int(batch_panel)
     o.batch_groups = int(batch_groups)
     return o
@@ -363,12 +362,12 @@ def pluq_last_stats():
 
 # ------------------------------------------------------------ convenience --
 
-def pluq(A, p: int, form="fp64", validate=False, cutoff=0, trsm_leaf=0):
+def pluq(A, p: int, form="fp64", validate=False, cutoff=0):
     """Decompose the device tensor A in place.  Returns (P, Q, r) with P, Q
     device int64 tensors."""
     import torch
     m, n = A.shape
     P = torch.empty(m, dtype=torch.int64, device=A.device)
     Q = torch.empty(n, dtype=torch.int64, device=A.device)
-    r = pluq_modp(A, p, P, Q, _opts(form, validate, cutoff, trsm_leaf))
+    r = pluq_modp(A, p, P, Q, _opts(form, validate, cutoff))
     return P, Q, r

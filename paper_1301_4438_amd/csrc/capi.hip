@@ -156,7 +156,7 @@ pluq_status check_common(int64_t m, int64_t n, int64_t lda, pluq_dtype dt, uint6
     if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
     if (o) {
         if (o->form != PLUQ_FORM_FP64 && o->form != PLUQ_FORM_INT8 && o->form != PLUQ_FORM_FP32) return PLUQ_ERR_ARG;
-        if (o->trsm_leaf_override < 0 || o->trsm_leaf_override > 64 || o->cutoff_override < 0) return PLUQ_ERR_ARG;
+        if (o->cutoff_override < 0) return PLUQ_ERR_ARG;
     }
     return PLUQ_OK;
 }
@@ -221,7 +221,6 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.form = form;
         c.kchunk = (int)std::min<int64_t>(fp64_kchunk(p), 1 << 30);
         c.kchunk32 = (int)fp32_kchunk(p);
-        c.leaf_nb = (opts && opts->trsm_leaf_override > 0) ? opts->trsm_leaf_override : 64;
         c.cap = bc_cap();
         if (c.cap <= 0) return PLUQ_ERR_DEVICE;
         if (opts && opts->cutoff_override > 0) c.cap = std::min<int64_t>(c.cap, opts->cutoff_override);

@@ -2,7 +2,8 @@
 //
 // node() follows the algorithm's block steps on the device-resident matrix:
 //   PLUQ(A1); PermR(A2, P1^T); PermC(A3, Q1^T);
-//   D <- L1^{-1} B1; E <- C1 U1^{-1}  (concurrently, on two streams);
+//   D <- L1^{-1} B1; E <- C1 U1^{-1}  (together: every launch of the two
+//                                      solves carries both, one stream);
 //   F <- B2 - M1 D; G <- C2 - E V1; H <- A4 - E D        (one grouped MM launch)
 //   PLUQ(F); PLUQ(G);
 //   H <- P3^T H Q2^T; E <- P3^T E; M1 <- P2^T M1; D <- D Q2^T; V1 <- V1 Q3^T;

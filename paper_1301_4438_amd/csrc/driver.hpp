@@ -71,7 +71,6 @@ struct Ctx {
     uint64_t p = 0;
     int form = 0;
     int kchunk = 16;
-    int leaf_nb = 64;
     int64_t cap = 16384;
     char *A = nullptr;
     int64_t lda = 0;

@@ -11,7 +11,9 @@
 // accumulator starts from C (loaded when the kernel starts, so no dependent
 // read is left for the end), A is negated on load, the accumulator is reduced
 // once per kchunk terms (delayed reduction, Section 6) and once before the
-// store.
+// store.  kchunk is at least 16 but may be below the panel depth BK (p near
+// 2^25 in float64, p above about 2^10 in float32): the RED16 instances then
+// reduce after every 16 products, at fixed points inside the panel.
 //
 // Tiling: 256 threads = 4 waves in a 2 x 2 grid; each wave owns a
 // (BM/2) x (BN/2) sub-tile made of 16 x 16 blocks computed with
@@ -60,7 +62,7 @@ struct MMArgs {
     ModP mod;
 };
 
-template <typename T, typename CT, int BM, int BN, int BK>
+template <typename T, typename CT, int BM, int BN, int BK, bool RED16>
 __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
     typedef MfmaTraits<CT> MT;
     constexpr int WM = BM / 2, WN = BN / 2;
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
                 acc[i][j][v] = (CT)to_f64(C[(int64_t)min(gr, M - 1) * P.ldc + min(gc, N - 1)]);
             }
 
+    static_assert(BK % 16 == 0, "RED16 reduces at multiples of 16 products");
     const int K0 = P.K[0], K1 = P.K[1];
     const int steps0 = (K0 + BK - 1) / BK;
     const int steps = steps0 + (K1 + BK - 1) / BK;
@@ -138,6 +141,15 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
         }
     };
 
+    auto reduce_acc = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[i][j][v] = (CT)mod_reduce((double)acc[i][j][v], mod);
+    };
+
     int kacc = 0;
     if (steps > 0) load_step(0);
     for (int s = 0; s < steps; ++s) {
@@ -156,13 +168,8 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
         }
         __syncthreads();
         if (s + 1 < steps) load_step(s + 1);
-        if (kacc + BK > args.kchunk) {
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[i][j][v] = (CT)mod_reduce((double)acc[i][j][v], mod);
+        if (!RED16 && kacc + BK > args.kchunk) {
+            reduce_acc();
             kacc = 0;
         }
 #pragma unroll
@@ -178,6 +185,8 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
                     acc[i][j] = MT::mfma(a[i], b[j], acc[i][j]);
+            // 16 products since the last reduction: at most kchunk
+            if (RED16 && (ks & 3) == 3) reduce_acc();
         }
         kacc += BK;
     }
@@ -202,7 +211,10 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
 
 template <typename T, typename CT, int BM, int BN, int BK>
 static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
-    PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK>), dim3(total), dim3(256), 0, st, args);
+    if (args.kchunk < BK)
+        PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK, true>), dim3(total), dim3(256), 0, st, args);
+    else
+        PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK, false>), dim3(total), dim3(256), 0, st, args);
     return hipGetLastError();
 }
 
@@ -217,6 +229,7 @@ static hipError_t launch_dt(MMArgs &args, int bm, int bn, int total, hipStream_t
 
 template <typename CT>
 static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
+    if (kchunk < 16 || kchunk % 16) return hipErrorInvalidValue;   // RED16 covers 16 products at a time
     MMArgs args;
     int n = 0;
     int64_t tiles128 = 0, tiles64 = 0;

@@ -47,7 +47,7 @@ def test_argument_errors():
     assert _call(5, 5, 5, 1, 1 << 26) == 2      # p too large
     assert _call(5, 5, 5, 1, 7, work_bytes=16) == 7
     assert _call(5, 5, 5, 1, 7, r=False) == 1
-    bad = pl._opts("fp64", trsm_leaf=65)
+    bad = pl._opts("fp64", cutoff=-1)
     assert _call(5, 5, 5, 1, 7, opts=bad) == 1
 
 

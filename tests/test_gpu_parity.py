@@ -144,8 +144,7 @@ def test_pluq_small_recursion(gpu_lib, cutoff):
         kind = kinds[trial % len(kinds)]
         A = _mixed_inputs(g, m, n, p, kind)
         note("pluq small", cutoff, trial, m, n, p, kind)
-        _check_pluq(gpu_lib, A, p, dtype=["int64", "float64", "int32"][trial % 3], cutoff=cutoff,
-                    trsm_leaf=[0, 3, 8][trial % 3])
+        _check_pluq(gpu_lib, A, p, dtype=["int64", "float64", "int32"][trial % 3], cutoff=cutoff)
 
 
 @pytest.mark.parametrize("kind", ["uniform", "lowrank", "planted", "sparse"])
@@ -208,3 +207,46 @@ def test_pluq_large_modulus(gpu_lib, dtype):
         A = _mixed_inputs(g, m, n, p, kind)
         note("pluq large p", kind, m, n, dtype)
         _check_pluq(gpu_lib, A, p, dtype=dtype)
+
+
+@pytest.mark.parametrize("p,form", [(33554393, "fp64"), (8388593, "fp64"), (2039, "fp32"), (1031, "fp32")])
+def test_modmm_delayed_reduction_worst_case(gpu_lib, p, form):
+    """Every operand +-(p-1)/2, so every product is the largest one of its
+    sign and partial sums grow as fast as they can: an update that sums
+    more products between reductions than the form's bound allows (kchunk,
+    as small as 16 here, below the panel depth of every tile shape) loses
+    exactness.  Inner dimensions of one and several panels; the last shape
+    has 128 x 128 tiles (32-deep panels), the others 64-deep panels."""
+    import torch
+    h = (p - 1) // 2
+    for sign in (1, -1):
+        for (m, n, k) in [(40, 40, 16), (40, 40, 64), (70, 70, 128), (130, 130, 200), (2048, 1920, 96)]:
+            note("modmm worst case", form, p, sign, m, n, k)
+            C = np.full((m, n), h, np.int64)
+            A = np.full((m, k), h, np.int64)
+            B = np.full((k, n), h if sign > 0 else p - h, np.int64)
+            Cd, Ad, Bd = _dev(C, "float64"), _dev(A, "float64"), _dev(B, "float64")
+            gpu_lib.pluq_modmm(Cd, Ad, Bd, p, form=form)
+            torch.cuda.synchronize()
+            assert np.array_equal(_np(Cd), oracle.mm(C, A, B, p)), (sign, m, n, k)
+
+
+@pytest.mark.parametrize("p,form", [(33554393, "fp64"), (2039, "fp32")])
+def test_pluq_extreme_entries(gpu_lib, p, form):
+    """Whole decompositions whose entries are all +-(p-1)/2 (random signs),
+    at the two moduli where the forms reduce after every 16 products."""
+    import torch
+    g = np.random.default_rng(p)
+    h = (p - 1) // 2
+    for (m, n) in [(300, 260), (700, 520)]:
+        A = np.where(g.random((m, n)) < 0.5, h, p - h).astype(np.int64)
+        note("pluq extreme entries", form, p, m, n)
+        Ad = _dev(A, "float64")
+        P = torch.empty(m, dtype=torch.int64, device="cuda")
+        Q = torch.empty(n, dtype=torch.int64, device="cuda")
+        r = gpu_lib.pluq_modp(Ad, p, P, Q, gpu_lib._opts(form))
+        torch.cuda.synchronize()
+        Po, Qo, ro, Xo = oracle.pluqz(A, p)
+        assert r == ro
+        assert np.array_equal(P.cpu().numpy(), Po) and np.array_equal(Q.cpu().numpy(), Qo)
+        assert np.array_equal(_np(Ad), Xo)
