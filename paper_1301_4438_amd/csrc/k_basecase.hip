@@ -1,6 +1,5 @@
 // Base case of the recursion: the decomposition of a tile of at most
-// TILE x TILE entries (TILE = 64 or 128), done by one work-group (256
-// threads; 512 for the elimination of a 128 x 128 tile).
+// 128 x 128 entries, done by one work-group.
 //
 // The output must be exactly the one Algorithm 1 would produce on the tile
 // (pivots in the order of its four recursive calls, non-pivot rows and
@@ -21,17 +20,16 @@
 // rank-profile pass is skipped.  The pivot order itself is computed on the
 // host between the two kernels (index bookkeeping only).
 //
-// Layout: with NT threads, thread (ty, tx) = (tid / 16, tid % 16) holds the
-// entries (ty + SY a, tx + 16 b), SY = NT / 16, in registers (RA x RB of
-// them), so the shrinking trailing block stays evenly spread over the
-// threads.  Register indices that depend on the step are resolved by
-// wave-uniform switches, never by indexing.
+// bc_lu runs one work-group of TILE / 16 waves per tile (TILE = 64 or 128),
+// blocked by panels of 16 columns, each factored inside one wave; bc_rpm
+// keeps the tile in registers, thread (ty, tx) = (tid / 16, tid % 16)
+// holding entries (ty + 16 a, tx + 16 b).  The layouts are described at each
+// kernel.
 // Pivot inverses come from an LDS table of inverses when p <= 65536, else
 // from the extended Euclidean algorithm.
-// Arithmetic uses delayed reduction (Section 6) inside the elimination: the
-// update is one FMA of symmetric residues on an exact integer-valued double,
-// an entry is reduced when it joins a pivot row or column, and every entry is
-// reduced after `kchunk` steps so that no accumulator exceeds 2^52.
+// Arithmetic uses delayed reduction (Section 6): products of symmetric
+// residues are accumulated exactly in float64 and reduced before any sum
+// could pass 2^52.
 #include <cmath>
 #include <type_traits>
 
@@ -41,9 +39,6 @@
 namespace pluq {
 
 constexpr int BC_THREADS = 256;
-// Threads of the elimination kernel for a tile: two waves per SIMD for the
-// 128 x 128 tile (32 entries per thread), one for the 64 x 64 tile.
-constexpr int bc_threads(int tile) { return tile > 64 ? 512 : 256; }
 constexpr int BC_DIM = 128;            // largest tile
 constexpr int BC_TAB_MAX = 65536;      // largest p with an LDS inverse table
 constexpr size_t BC_TAB_BYTES = BC_TAB_MAX * sizeof(uint16_t);
@@ -55,54 +50,113 @@ __global__ __launch_bounds__(256) void build_inv_table_kernel(uint16_t *tab, Mod
     if (a < p) tab[a] = (uint16_t)(a == 0 ? 0 : (int)mod_inv((double)a, mod));
 }
 
-// bc_lu step structure (one step = one pivot s):
-//   P1  every thread finalises one entry of the pivot row or column: reads
-//       its raw value from LDS, reduces it and publishes the symmetric
-//       residue used by the update (the multipliers are the column scaled by
-//       the pivot's inverse, which each thread looks up itself);
-//   P2  every thread applies the rank-one update to its registers with
-//       branch-free FMAs (inactive rows and columns were published as zero),
-//       and the owners of row and column s+1 copy them to LDS for the next P1.
-// Two barriers per step.  Once a row or column has been a pivot row or
-// column its registers are never changed again (it is published as zero),
-// so the result is read from the registers at the end: U entries reduced,
-// L entries reduced and multiplied by their pivot's inverse (kept in LDS).
-// A is written only on success, so a failed optimistic attempt leaves the
-// input untouched.
-struct BcShared {
-    double row[BC_DIM];   // raw entries of the next pivot row
-    double col[BC_DIM];   // raw entries of the next pivot column
-    double Lb[BC_DIM];    // published multipliers (symmetric)
-    double Ub[BC_DIM];    // published pivot row (symmetric)
-    double inv[BC_DIM];   // inverse of each pivot
-};
+// bc_lu: elimination without pivoting of a tile, blocked by panels of 16
+// columns.  With TILE x TILE the tile size (64 or 128) there are NW =
+// TILE / 16 waves; wave w owns column block w (columns 16w .. 16w+15) for the
+// whole tile, held as NW matrix-core accumulator blocks of 16 x 16 (lane
+// holds rows (lane / 16) + 4v, column lane % 16 of each block).
+//
+// Panel k (columns c0 = 16k .. c0+15) is factored by its owner, wave k, on
+// its own: the column block goes through LDS into a row layout (lane l holds
+// rows l and l + 64, all 16 columns) and the 16 steps run with the pivot row
+// broadcast by lane reads, with no work-group barrier per pivot.  The steps
+// are free of branches (a zero pivot, or the end of the steps asked for,
+// turns the remaining steps into no-ops through their multipliers) and each
+// updates the next pivot column first, so that the next pivot's reduction
+// and table lookup overlap the update of the other columns.  The owner then
+// publishes the negated multipliers below the panel (L21) and the panel's
+// four block-column eliminators M_c (c = 0..3, 16 x 4 each): with D_c the
+// unit lower 4 x 4 diagonal block of L11 at columns 4c..4c+3, M_c holds
+// D_c^-1 - I in the chunk's rows and -L11[below, 4c..4c+3] D_c^-1 below them,
+// so that A12 <- A12 + M_c A12[4c..4c+3], taken for c = 0..3, leaves
+// U12 = L11^-1 A12.  After one barrier every later wave w forms its block of
+// U12 that way (four matrix-core products) and applies the rank-16 update
+// A22 <- A22 - L21 U12 to its column block with v_mfma_f64_16x16x4: a block
+// row of the accumulator is already in the operand layout the instruction
+// takes for B, so no data moves between the products.  The owner of the
+// next panel does its own update first (at a raised wave priority) and goes
+// on to factor while the others update theirs.  The published panels are
+// double-buffered, so one barrier per panel suffices.  Values cross LDS as
+// float: symmetric residues are at most p/2 + 1 <= 2^24 in magnitude for
+// p < 2^25, exact in float.
+//
+// A zero pivot at step s (or the end of the r_known steps of an ordered
+// elimination) ends the panel there: the owner publishes the steps done so
+// far (zero multipliers in the remaining columns, an identity part of L11),
+// the other waves apply that partial update, and the block left at (s, s)
+// is tested for zero across the work-group: the identity order is right
+// exactly when it is zero (r = s).
+// Delayed reduction (Section 6): every quantity that enters a product is a
+// symmetric residue, the panel accumulates at most 15 rank-one updates, the
+// U12 chunks at most 12 products, and the trailing blocks are reduced before an update
+// whenever kchunk products could be exceeded (every 8 products for p close
+// to 2^25).
+// The result goes through LDS (canonical residues as int32, over the
+// inverse table, which is no longer needed) and is stored with whole rows
+// per instruction.  A is written only on success, so a failed optimistic
+// attempt leaves the input untouched.
 
-__device__ __forceinline__ double bc_inverse(double x, const ModP &mod, const uint16_t *tab) {
-    if (x == 0.0) return 0.0;
-    return tab ? (double)tab[(int)x] : mod_inv(x, mod);
+typedef double bc_v4d __attribute__((ext_vector_type(4)));
+
+// Value of x held by lane `src` (wave-uniform), for every lane.
+__device__ __forceinline__ double bc_lane(double x, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+    return __hiloint2double(hi, lo);
 }
 
-template <typename T, int TILE, int NT>
-__global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int n, const int32_t *rmap,
-                                                   const int32_t *cmap, int r_known, ModP mod, int kchunk,
-                                                   const uint16_t *gtab, int32_t *status, int32_t *specfail,
-                                                   int32_t *errflag) {
-    constexpr int SY = NT / 16;       // row stride of a thread's entries
-    constexpr int RA = TILE / SY;     // rows per thread
-    constexpr int RB = TILE / 16;     // columns per thread
+// Order of this wave's own LDS accesses (one wave's LDS instructions are
+// executed in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void bc_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Symmetric reduction x - round(x / p) p with the quotient rounded by adding
+// and subtracting 1.5 * 2^52 (one fused multiply-add forms x / p + 1.5 * 2^52
+// with a single rounding, which lands on an integer for |x / p| < 2^51):
+// three full-rate operations, the same result bounds as sym_reduce
+// (magnitude at most p/2 + 1, zero exactly when p divides x, |x| < 2^52).
+__device__ __forceinline__ double bc_sym(double x, const ModP &m) {
+    constexpr double MAGIC = 6755399441055744.0;
+    const double q = fma(x, m.pinv, MAGIC) - MAGIC;
+    return fma(-q, m.p, x);
+}
+
+constexpr int BC_XS = 17;                            // padded row stride (floats) of the panel buffers
+constexpr int BC_OUT_BYTES = BC_DIM * (BC_DIM + 1) * 4;   // int32 result tile staged in LDS
+
+template <int TILE> struct BcBlkShared {
+    float xb[TILE * BC_XS];          // owner's column block, transposed (owner only)
+    float pl[2][TILE * BC_XS];       // published panel: -L21 below it
+    float pi[2][16 * BC_XS];         // published chunk eliminators M_0..M_3
+    int flag[2][2];                  // steps done in the panel, zero pivot hit
+};
+
+template <typename T, int TILE, bool TAB>
+__global__ __launch_bounds__(TILE * 4) void bc_lu_kernel(T *A, int64_t lda, int m, int n, const int32_t *rmap,
+                                                         const int32_t *cmap, int r_known, ModP mod, int kchunk,
+                                                         const uint16_t *gtab, int32_t *status, int32_t *specfail,
+                                                         int32_t *errflag) {
+    constexpr int NW = TILE / 16;   // waves = column blocks = block rows
+    constexpr int NT = 64 * NW;
+    constexpr int NH = TILE / 64;   // rows per lane in the row layout
+    constexpr int XS = BC_XS;
+    constexpr int OS = TILE + 1;    // row stride of the staged result
     extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ BcShared sh;
+    __shared__ BcBlkShared<TILE> sh;
     const int tid = threadIdx.x;
-    const int ty = tid >> 4, tx = tid & 15;
-    const uint16_t *tab = nullptr;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lq = lane >> 4;
+    const uint16_t *tab = (const uint16_t *)dyn;
 
     // copy the inverse table (16-byte words, in flight together)
-    if (gtab) {
+    if (TAB) {
         const int words = ((int)mod.p + 7) / 8;
         const uint4 *src = (const uint4 *)gtab;
         uint4 *dst = (uint4 *)dyn;
-        constexpr int PER = BC_TAB_MAX / 8 / NT;           // 16-byte words per thread
-        constexpr int CH = 8;                               // loads in flight per thread
+        constexpr int PER = BC_TAB_MAX / 8 / NT;
+        constexpr int CH = 8;
 #pragma unroll
         for (int k0 = 0; k0 < PER; k0 += CH) {
             uint4 tmp[CH];
@@ -117,255 +171,303 @@ __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int
                 if (w < words) dst[w] = tmp[k];
             }
         }
-        tab = (const uint16_t *)dyn;
     }
 
-    double v[RA][RB];
+    // the column block of this wave, in accumulator layout: row indices
+    // first (all in flight), then the entries (clamped addresses, all in
+    // flight), then out-of-range entries masked to zero
+    bc_v4d acc[NW];
+    {
+        const int j = 16 * wave + lr;
+        const bool jin = j < n;
+        const int jc = jin ? j : n - 1;
+        const int64_t gj = cmap ? cmap[jc] : jc;
+        int32_t ri[NW][4];
+        if (rmap) {
 #pragma unroll
-    for (int a = 0; a < RA; ++a) {
-        const int i = ty + SY * a;
-        const int64_t gi = (i < m) ? (rmap ? rmap[i] : i) : 0;
+            for (int b = 0; b < NW; ++b)
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            const int j = tx + 16 * b;
-            double x = 0.0;
-            if (i < m && j < n) x = to_f64(A[gi * lda + (cmap ? cmap[j] : j)]);
-            v[a][b] = x;
+                for (int v = 0; v < 4; ++v) ri[b][v] = rmap[min(16 * b + lq + 4 * v, m - 1)];
+        } else {
+#pragma unroll
+            for (int b = 0; b < NW; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ri[b][v] = min(16 * b + lq + 4 * v, m - 1);
         }
-    }
-    if (ty == 0) {
+        T raw[NW][4];
 #pragma unroll
-        for (int b = 0; b < RB; ++b) sh.row[tx + 16 * b] = v[0][b];
-    }
-    if (tx == 0) {
+        for (int b = 0; b < NW; ++b)
 #pragma unroll
-        for (int a = 0; a < RA; ++a) sh.col[ty + SY * a] = v[a][0];
+            for (int v = 0; v < 4; ++v) raw[b][v] = A[(int64_t)ri[b][v] * lda + gj];
+#pragma unroll
+        for (int b = 0; b < NW; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[b][v] = (jin && 16 * b + lq + 4 * v < m) ? to_f64(raw[b][v]) : 0.0;
     }
-    __syncthreads();
+    if (TAB) __syncthreads();   // the table is in LDS
+    // After a wave has factored its panel, the same registers hold its column
+    // block in row layout: rows lane + 64h, columns 16 wave + j.
+#define RR(h, j) acc[((h) * 16 + (j)) >> 2][((h) * 16 + (j)) & 3]
 
     const int kmax = m < n ? m : n;
     const int steps = r_known >= 0 ? r_known : kmax;
-    int r = steps;
-    bool ok = true, stop = false;
+    const double p = mod.p;
+    // trailing blocks get at most 16 products per panel: reduce them before
+    // each update unless NW - 1 updates fit in kchunk; every 8 products when
+    // 16 do not
+    const bool red_each = kchunk < 16 * NW;
+    const bool red8 = kchunk < 16;
 
-    // One elimination step s whose row and column s+1 sit in register row
-    // block QA and column block QB (compile-time constants, so the publish
-    // needs no switch).  Returns false at a zero pivot (r and ok set).
-    auto step = [&](int s, auto QA, auto QB) __attribute__((always_inline)) -> bool {
-        constexpr int qa = decltype(QA)::value, qb = decltype(QB)::value;
-        double piv = sym_reduce(sh.row[s], mod);
-        if (piv == 0.0) {
-            // zero pivot at (s, s): the identity order is right iff the rest is zero
-            int any = 0;
+    int r = 0, klast = -1;
+    bool zero_hit = false;
+    for (int k = 0; k < NW; ++k) {
+        const int c0 = 16 * k;
+        if (c0 >= steps) break;   // steps == 0 only (otherwise the exit below)
+        const int buf = k & 1;
+        if (wave == k) {
+            // ---- owner: column block -> row layout
 #pragma unroll
-            for (int a = 0; a < RA; ++a)
+            for (int b = 0; b < NW; ++b)
 #pragma unroll
-                for (int b = 0; b < RB; ++b) {
-                    const int i = ty + SY * a, j = tx + 16 * b;
-                    if (i >= s && j >= s && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
+                for (int v = 0; v < 4; ++v)
+                    sh.xb[(16 * b + lq + 4 * v) * XS + lr] = (float)bc_sym(acc[b][v], mod);
+            bc_wave_sync();
+#pragma unroll
+            for (int h = 0; h < NH; ++h)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) RR(h, j) = (double)sh.xb[(lane + 64 * h) * XS + j];
+            bc_wave_sync();
+            // ---- factor the panel: steps s = c0 + C while s < steps and no
+            // zero pivot has been met (later steps have zero multipliers);
+            // cd counts the steps done, zh records a zero pivot
+            int cd = 0;
+            bool zh = false;
+            double X[16];   // this lane's row of the chunk matrices M_c (below)
+            auto factor = [&](auto HS) __attribute__((always_inline)) {
+                constexpr int hs = decltype(HS)::value;
+                // Pivot of step s (its row and column updated through step
+                // s - 1): whether the step runs (good) and the inverse (0
+                // when it does not, so that its multipliers vanish).
+                bool good;
+                double inv;
+                auto pivot = [&](int s, double raw, bool alive) __attribute__((always_inline)) {
+                    double pv = bc_sym(raw, mod);
+                    pv = (pv < 0.0) ? pv + p : pv;
+                    const bool run = alive && s < steps;
+                    good = run && pv != 0.0;
+                    zh = zh || (run && pv == 0.0);
+                    if constexpr (TAB) inv = (double)tab[good ? (int)pv : 0];
+                    else inv = mod_inv(good ? pv : 0.0, mod);
+                };
+                pivot(c0, bc_lane(RR(hs, 0), c0 & 63), true);
+                // Step C: multipliers of column C, then the update of column
+                // C + 1 and the next pivot (its reduction and inverse in
+                // flight) before the update of the other columns.
+                auto step = [&](auto CC) __attribute__((always_inline)) {
+                    constexpr int C = decltype(CC)::value;
+                    const int s = c0 + C;
+                    cd = good ? C + 1 : cd;
+                    // pivot row s, reduced in place, read from its lane
+#pragma unroll
+                    for (int j = C + 1; j < 16; ++j) RR(hs, j) = bc_sym(RR(hs, j), mod);
+                    double u[16];
+#pragma unroll
+                    for (int j = C + 1; j < 16; ++j) u[j] = bc_lane(RR(hs, j), s & 63);
+                    double lv[NH];
+#pragma unroll
+                    for (int h = hs; h < NH; ++h) {   // halves below hs hold rows above the panel
+                        const bool act = good && lane + 64 * h > s;
+                        // |x| <= p/2 + 1 + 15 (p/2 + 1)^2, so x * inv < 2^52 for
+                        // p <= 65536 without reducing x first
+                        const double x = TAB ? RR(h, C) : bc_sym(RR(h, C), mod);
+                        const double l = bc_sym(x * inv, mod);
+                        lv[h] = act ? l : 0.0;
+                        RR(h, C) = act ? l : RR(h, C);
+                    }
+                    if constexpr (C + 1 < 16) {
+#pragma unroll
+                        for (int h = hs; h < NH; ++h) RR(h, C + 1) = fma(-lv[h], u[C + 1], RR(h, C + 1));
+                        pivot(s + 1, bc_lane(RR(hs, C + 1), (s + 1) & 63), good);
+#pragma unroll
+                        for (int h = hs; h < NH; ++h)
+#pragma unroll
+                            for (int j = C + 2; j < 16; ++j) RR(h, j) = fma(-lv[h], u[j], RR(h, j));
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                };
+#define PLUQ_S(C) step(std::integral_constant<int, C>{})
+                PLUQ_S(0); PLUQ_S(1); PLUQ_S(2); PLUQ_S(3); PLUQ_S(4); PLUQ_S(5); PLUQ_S(6); PLUQ_S(7);
+                PLUQ_S(8); PLUQ_S(9); PLUQ_S(10); PLUQ_S(11); PLUQ_S(12); PLUQ_S(13); PLUQ_S(14); PLUQ_S(15);
+#undef PLUQ_S
+                // ---- the panel's block-column eliminators, 4 columns at a
+                // time: with D_c the unit lower 4 x 4 diagonal block of L11 at
+                // columns 4c..4c+3 (entries of the steps done only), row t of
+                // M_c is (D_c^-1 - I)[t - 4c] inside the chunk, -L[t][4c..]
+                // D_c^-1 below it and 0 above, so that the update
+                // A12 <- A12 + M_c A12[4c..4c+3] taken for c = 0..3 leaves
+                // U12 = L11^-1 A12.  This lane forms the 16 entries of its
+                // row t = lane + 64 hs - c0 (meaningful for the panel's rows).
+                const int cdu = __builtin_amdgcn_readfirstlane(cd);
+                const int t = lane + 64 * hs - c0;
+                // with this row's multipliers masked to the columns q < t
+                // (and to the steps done), -sum_{q >= g} L[t][4c+q] D_c^-1[q][g]
+                // is D_c^-1[t-4c][g] for g < t - 4c inside the chunk, 0 on and
+                // above its diagonal, the entry below it, and 0 above it
+                const int qlim = min(t, cdu);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    // D_c's strict lower entries, from the rows' lanes
+                    auto Lq = [&](int g, int q) __attribute__((always_inline)) {
+                        const double x = bc_lane(RR(hs, 4 * c + q), (c0 + 4 * c + g) & 63);
+                        return (4 * c + q < cdu) ? x : 0.0;
+                    };
+                    const double a10 = Lq(1, 0), a20 = Lq(2, 0), a21 = Lq(2, 1), a30 = Lq(3, 0), a31 = Lq(3, 1),
+                                 a32 = Lq(3, 2);
+                    // D_c^-1 by forward substitution (unit diagonal)
+                    const double i10 = -a10;
+                    const double i21 = -a21;
+                    const double i20 = -bc_sym(fma(a21, i10, a20), mod);
+                    const double i32 = -a32;
+                    const double i31 = -bc_sym(fma(a32, i21, a31), mod);
+                    const double i30 = -bc_sym(fma(a32, i20, fma(a31, i10, a30)), mod);
+                    const double Di[4][4] = {{1.0, 0.0, 0.0, 0.0}, {i10, 1.0, 0.0, 0.0}, {i20, i21, 1.0, 0.0},
+                                             {i30, i31, i32, 1.0}};
+                    double lt[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) lt[q] = (4 * c + q < qlim) ? RR(hs, 4 * c + q) : 0.0;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        double d = 0.0;
+#pragma unroll
+                        for (int q = g; q < 4; ++q) d = fma(lt[q], Di[q][g], d);
+                        X[4 * c + g] = -bc_sym(d, mod);
+                    }
                 }
-            any = __syncthreads_or(any);
-            ok = (any == 0) && (r_known < 0);
-            r = s;
-            return false;
-        }
-        if (piv < 0.0) piv += mod.p;   // canonical, for the inverse
-        const double inv = bc_inverse(piv, mod, tab);
-        if (tid < TILE) {
-            const int j = tid;
-            const double u = sym_reduce(sh.row[j], mod);
-            sh.Ub[j] = (j > s && j < n) ? u : 0.0;
-            if (j == 0) sh.inv[s] = inv;
-        } else if (tid < 2 * TILE) {
-            const int i = tid - TILE;
-            const bool act = (i > s) && (i < m);
-            const double l = sym_reduce(sym_reduce(sh.col[i], mod) * inv, mod);
-            sh.Lb[i] = act ? l : 0.0;
+            };
+            if constexpr (NH == 1) {
+                factor(std::integral_constant<int, 0>{});
+            } else {
+                if (c0 < 64) factor(std::integral_constant<int, 0>{});
+                else factor(std::integral_constant<int, 1>{});
+            }
+            // ---- publish -L21 (the steps done; zero columns after them;
+            // rows above the panel are written too but never read) and the
+            // chunk matrices M_c
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                const int i = lane + 64 * h;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    sh.pl[buf][i * XS + j] = (i >= c0 + 16 && j < cd) ? -(float)RR(h, j) : 0.0f;
+            }
+            {
+                const int t = lane + 64 * (c0 >> 6) - c0;
+                if (t >= 0 && t < 16) {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) sh.pi[buf][t * XS + q] = (float)X[q];
+                }
+            }
+            if (lane == 0) {
+                sh.flag[buf][0] = cd;
+                sh.flag[buf][1] = zh ? 1 : 0;
+            }
         }
         __syncthreads();
-        double l[RA], u[RB];
+        const int cd = sh.flag[buf][0];
+        const bool zh = sh.flag[buf][1] != 0;
+        if (wave > k) {
+            // ---- U12 = L11^-1 A12 (four chunk products M_c A12[4c..4c+3],
+            // each chunk reduced before it is used) and A22 <- A22 - L21 U12
+            // for this column block
+            const float *Mi = sh.pi[buf];
+            const float *Lp = sh.pl[buf];
+            auto update = [&](auto KK) __attribute__((always_inline)) {
+                constexpr int K = decltype(KK)::value;
+                float mi[4], la[NW][4];
 #pragma unroll
-        for (int a = 0; a < RA; ++a) l[a] = sh.Lb[ty + SY * a];
+                for (int c = 0; c < 4; ++c) mi[c] = Mi[lr * XS + 4 * c + lq];
 #pragma unroll
-        for (int b = 0; b < RB; ++b) u[b] = sh.Ub[tx + 16 * b];
+                for (int b = K + 1; b < NW; ++b)
 #pragma unroll
-        for (int a = 0; a < RA; ++a)
+                    for (int c = 0; c < 4; ++c) la[b][c] = Lp[(16 * b + lr) * XS + 4 * c + lq];
+                bc_v4d u = acc[K];
+                u[0] = bc_sym(u[0], mod);
 #pragma unroll
-            for (int b = 0; b < RB; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
-        if (s + 1 < steps) {
-            const int t = s + 1;
-            if (ty == t % SY) {
-#pragma unroll
-                for (int b = 0; b < RB; ++b) sh.row[tx + 16 * b] = v[qa][b];
-            }
-            if (tx == (t & 15)) {
-#pragma unroll
-                for (int a = 0; a < RA; ++a) sh.col[ty + SY * a] = v[a][qb];
-            }
-        }
-        __syncthreads();
-        return true;
-    };
-
-    if (kchunk >= steps) {
-        // No full-tile reduction needed: the steps run in blocks of 16 by the
-        // index t = s + 1 of the row and column they publish, which sit in
-        // register column block t / 16 and row block t / SY, unrolled.
-#define PLUQ_BC_BLOCK(K)                                                                          \
-    if constexpr ((K) < RB) {                                                                     \
-        if (!stop) {                                                                              \
-            const int tlo = (K) * 16 < 1 ? 1 : (K) * 16;                                          \
-            const int thi = (K) * 16 + 16 <= steps ? (K) * 16 + 16 : steps + 1;                   \
-            for (int t = tlo; t < thi; ++t) {                                                     \
-                if (!step(t - 1, std::integral_constant<int, ((K) * 16) / SY>{},                  \
-                          std::integral_constant<int, (K)>{})) {                                  \
-                    stop = true;                                                                  \
-                    break;                                                                        \
-                }                                                                                 \
-            }                                                                                     \
-        }                                                                                         \
-    }
-        PLUQ_BC_BLOCK(0)
-        PLUQ_BC_BLOCK(1)
-        PLUQ_BC_BLOCK(2)
-        PLUQ_BC_BLOCK(3)
-        PLUQ_BC_BLOCK(4)
-        PLUQ_BC_BLOCK(5)
-        PLUQ_BC_BLOCK(6)
-        PLUQ_BC_BLOCK(7)
-#undef PLUQ_BC_BLOCK
-        // the last step of a full tile (s = TILE - 1 publishes nothing)
-        if (!stop && steps == 16 * RB) {
-            if (!step(steps - 1, std::integral_constant<int, 0>{}, std::integral_constant<int, 0>{})) stop = true;
-        }
-    } else {
-    // Steps are taken in chunks of kchunk with a full-tile reduction between
-    // chunks, so that the loop over the steps of a chunk carries the tile
-    // registers through unchanged (a conditional reduction inside it makes
-    // the compiler keep two copies of the tile).
-    for (int s0 = 0; s0 < steps && !stop; s0 += kchunk) {
-    const int s1 = (steps - s0 > kchunk) ? s0 + kchunk : steps;
-    for (int s = s0; s < s1; ++s) {
-        // ---- P1
-        double piv = sym_reduce(sh.row[s], mod);
-        if (piv == 0.0) {
-            // zero pivot at (s, s): the identity order is right iff the rest is zero
-            int any = 0;
-#pragma unroll
-            for (int a = 0; a < RA; ++a)
-#pragma unroll
-                for (int b = 0; b < RB; ++b) {
-                    const int i = ty + SY * a, j = tx + 16 * b;
-                    if (i >= s && j >= s && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
+                for (int c = 0; c < 4; ++c) {
+                    u = __builtin_amdgcn_mfma_f64_16x16x4f64((double)mi[c], u[c], u, 0, 0, 0);
+                    if (c < 3) u[c + 1] = bc_sym(u[c + 1], mod);
                 }
-            any = __syncthreads_or(any);
-            ok = (any == 0) && (r_known < 0);
-            r = s;
-            stop = true;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) u[v] = bc_sym(u[v], mod);
+                acc[K] = u;
+                if (red_each) {
+#pragma unroll
+                    for (int b = K + 1; b < NW; ++b)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[b][v] = bc_sym(acc[b][v], mod);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int b = K + 1; b < NW; ++b)
+                        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)la[b][c], u[c], acc[b], 0, 0, 0);
+                    if (c == 1 && red8) {
+#pragma unroll
+                        for (int b = K + 1; b < NW; ++b)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc[b][v] = bc_sym(acc[b][v], mod);
+                    }
+                }
+            };
+            // the owner of the next panel goes first on its SIMD
+            if (wave == k + 1) __builtin_amdgcn_s_setprio(2);
+            switch (k) {
+            case 0: update(std::integral_constant<int, 0>{}); break;
+            case 1: if constexpr (NW > 1) update(std::integral_constant<int, 1>{}); break;
+            case 2: if constexpr (NW > 2) update(std::integral_constant<int, 2>{}); break;
+            case 3: if constexpr (NW > 3) update(std::integral_constant<int, 3>{}); break;
+            case 4: if constexpr (NW > 4) update(std::integral_constant<int, 4>{}); break;
+            case 5: if constexpr (NW > 5) update(std::integral_constant<int, 5>{}); break;
+            case 6: if constexpr (NW > 6) update(std::integral_constant<int, 6>{}); break;
+            default: break;
+            }
+            if (wave == k + 1) __builtin_amdgcn_s_setprio(0);
+        }
+        klast = k;
+        if (zh || c0 + cd >= steps) {
+            r = c0 + cd;
+            zero_hit = zh;
             break;
         }
-        if (piv < 0.0) piv += mod.p;   // canonical, for the inverse
-        const double inv = bc_inverse(piv, mod, tab);
-        if (tid < TILE) {
-            const int j = tid;
-            const double u = sym_reduce(sh.row[j], mod);
-            sh.Ub[j] = (j > s && j < n) ? u : 0.0;
-            if (j == 0) sh.inv[s] = inv;
-        } else if (tid < 2 * TILE) {
-            const int i = tid - TILE;
-            const bool act = (i > s) && (i < m);
-            const double l = sym_reduce(sym_reduce(sh.col[i], mod) * inv, mod);
-            sh.Lb[i] = act ? l : 0.0;
-        }
-        __syncthreads();
-        // ---- P2
-        double l[RA], u[RB];
-#pragma unroll
-        for (int a = 0; a < RA; ++a) l[a] = sh.Lb[ty + SY * a];
-#pragma unroll
-        for (int b = 0; b < RB; ++b) u[b] = sh.Ub[tx + 16 * b];
-#pragma unroll
-        for (int a = 0; a < RA; ++a)
-#pragma unroll
-            for (int b = 0; b < RB; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
-        if (s + 1 < steps) {
-            // owners of row / column s+1 copy them to LDS; the register
-            // indices (s+1)/SY and (s+1)/16 are wave-uniform and resolved by
-            // the switches
-            const int t = s + 1;
-#define PLUQ_BC_ROW(Q)                                                                        \
-    if constexpr ((Q) < RA) {                                                                 \
-        if (ty == t % SY) {                                                                   \
-            _Pragma("unroll") for (int b = 0; b < RB; ++b) sh.row[tx + 16 * b] = v[(Q)][b];   \
-        }                                                                                     \
     }
-#define PLUQ_BC_COL(Q)                                                                        \
-    if constexpr ((Q) < RB) {                                                                 \
-        if (tx == (t & 15)) {                                                                 \
-            _Pragma("unroll") for (int a = 0; a < RA; ++a) sh.col[ty + SY * a] = v[a][(Q)];   \
-        }                                                                                     \
-    }
-            if constexpr (SY == 16) {
-                // one switch: row and column s+1 sit at the same register index
-                switch (t >> 4) {
-                case 0: PLUQ_BC_ROW(0) PLUQ_BC_COL(0) break;
-                case 1: PLUQ_BC_ROW(1) PLUQ_BC_COL(1) break;
-                case 2: PLUQ_BC_ROW(2) PLUQ_BC_COL(2) break;
-                case 3: PLUQ_BC_ROW(3) PLUQ_BC_COL(3) break;
-                case 4: PLUQ_BC_ROW(4) PLUQ_BC_COL(4) break;
-                case 5: PLUQ_BC_ROW(5) PLUQ_BC_COL(5) break;
-                case 6: PLUQ_BC_ROW(6) PLUQ_BC_COL(6) break;
-                case 7: PLUQ_BC_ROW(7) PLUQ_BC_COL(7) break;
-                default: break;
-                }
-            } else {
-                switch (t / SY) {
-                case 0: PLUQ_BC_ROW(0) break;
-                case 1: PLUQ_BC_ROW(1) break;
-                case 2: PLUQ_BC_ROW(2) break;
-                case 3: PLUQ_BC_ROW(3) break;
-                case 4: PLUQ_BC_ROW(4) break;
-                case 5: PLUQ_BC_ROW(5) break;
-                case 6: PLUQ_BC_ROW(6) break;
-                case 7: PLUQ_BC_ROW(7) break;
-                default: break;
-                }
-                switch (t >> 4) {
-                case 0: PLUQ_BC_COL(0) break;
-                case 1: PLUQ_BC_COL(1) break;
-                case 2: PLUQ_BC_COL(2) break;
-                case 3: PLUQ_BC_COL(3) break;
-                case 4: PLUQ_BC_COL(4) break;
-                case 5: PLUQ_BC_COL(5) break;
-                case 6: PLUQ_BC_COL(6) break;
-                case 7: PLUQ_BC_COL(7) break;
-                default: break;
-                }
-            }
-#undef PLUQ_BC_ROW
-#undef PLUQ_BC_COL
-        }
-        __syncthreads();
-    }
-    if (!stop && s1 < steps) {
-#pragma unroll
-        for (int a = 0; a < RA; ++a)
-#pragma unroll
-            for (int b = 0; b < RB; ++b) v[a][b] = sym_reduce(v[a][b], mod);
-    }
-    }
-    }
-    if (ok && r_known >= 0 && r < kmax) {
-        // the rank is known: the block left after it must be zero
+
+    // The block left at (r, r) must be zero after a zero pivot (optimistic
+    // attempt) or when fewer than min(m, n) steps were asked for.
+    bool ok = !(zero_hit && r_known >= 0);
+    const bool test = ok && (zero_hit || r < kmax);
+    const bool rowlayout = wave <= klast;
+    if (test) {
         int any = 0;
+        if (rowlayout) {
 #pragma unroll
-        for (int a = 0; a < RA; ++a)
+            for (int h = 0; h < NH; ++h)
 #pragma unroll
-            for (int b = 0; b < RB; ++b) {
-                const int i = ty + SY * a, j = tx + 16 * b;
-                if (i >= r && j >= r && i < m && j < n) any |= (sym_reduce(v[a][b], mod) != 0.0);
-            }
+                for (int j = 0; j < 16; ++j) {
+                    const int i = lane + 64 * h, jg = 16 * wave + j;
+                    if (i >= r && jg >= r && i < m && jg < n) any |= (bc_sym(RR(h, j), mod) != 0.0);
+                }
+        } else {
+#pragma unroll
+            for (int b = 0; b < NW; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * b + lq + 4 * v, jg = 16 * wave + lr;
+                    if (i >= r && jg >= r && i < m && jg < n) any |= (bc_sym(acc[b][v], mod) != 0.0);
+                }
+        }
         ok = __syncthreads_or(any) == 0;
+    } else {
+        __syncthreads();   // every wave is past the table before it is overwritten
     }
     // speculative use (the caller assumed a full-rank tile in the identity
     // order): record a failed assumption in the sticky flag
@@ -376,17 +478,39 @@ __global__ __launch_bounds__(NT) void bc_lu_kernel(T *A, int64_t lda, int m, int
         if (tid == 0) { status[0] = r; status[1] = 0; }
         return;
     }
+    // canonical residues into the LDS tile, then whole rows to A
+    int32_t *out = (int32_t *)dyn;
+    if (rowlayout) {
 #pragma unroll
-    for (int a = 0; a < RA; ++a) {
-        const int i = ty + SY * a;
+        for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            const int j = tx + 16 * b;
-            if (i < m && j < n) {
-                double x = mod_reduce(v[a][b], mod);
-                if (j < r && i > j) x = mod_mul(x, sh.inv[j], mod);   // L entry
-                A[(int64_t)i * lda + j] = from_f64<T>(x);
+            for (int j = 0; j < 16; ++j) out[(lane + 64 * h) * OS + 16 * wave + j] = (int32_t)mod_reduce(RR(h, j), mod);
+    } else {
+#pragma unroll
+        for (int b = 0; b < NW; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(16 * b + lq + 4 * v) * OS + 16 * wave + lr] = (int32_t)mod_reduce(acc[b][v], mod);
+    }
+#undef RR
+    __syncthreads();
+    constexpr int VE = 16 / (int)sizeof(T);   // elements per 16-byte store
+    struct alignas(16) Vec { T x[VE]; };
+    if (n == TILE && lda % VE == 0 && ((uintptr_t)A & 15) == 0) {
+#pragma unroll
+        for (int e = 0; e < TILE * TILE / VE / NT; ++e) {
+            const int idx = (tid + NT * e) * VE;
+            const int i = idx / TILE, j = idx % TILE;
+            if (i < m) {
+                Vec o;
+#pragma unroll
+                for (int q = 0; q < VE; ++q) o.x[q] = from_f64<T>((double)out[i * OS + j + q]);
+                *(Vec *)&A[(int64_t)i * lda + j] = o;
             }
+        }
+    } else {
+        for (int idx = tid; idx < m * n; idx += NT) {
+            const int i = idx / n, j = idx - i * n;
+            A[(int64_t)i * lda + j] = from_f64<T>((double)out[i * OS + j]);
         }
     }
     if (tid == 0) { status[0] = r; status[1] = 1; }
@@ -562,12 +686,12 @@ hipError_t bc_init() {
     if (hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize,               \
                             (int)BC_TAB_BYTES) != hipSuccess)                                           \
         g_tab_ok = false;
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64, bc_threads(64)>))
-    PLUQ_SETLDS((bc_lu_kernel<double, 64, bc_threads(64)>))
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64, bc_threads(64)>))
-    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, bc_threads(128)>))
-    PLUQ_SETLDS((bc_lu_kernel<double, 128, bc_threads(128)>))
-    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, bc_threads(128)>))
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 64, true>))
+    PLUQ_SETLDS((bc_lu_kernel<double, 64, true>))
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 64, true>))
+    PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, true>))
+    PLUQ_SETLDS((bc_lu_kernel<double, 128, true>))
+    PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, true>))
     PLUQ_SETLDS((bc_rpm_kernel<int64_t, false>))
     PLUQ_SETLDS((bc_rpm_kernel<double, false>))
     PLUQ_SETLDS((bc_rpm_kernel<int32_t, false>))
@@ -575,10 +699,22 @@ hipError_t bc_init() {
     PLUQ_SETLDS((bc_rpm_kernel<double, true>))
     PLUQ_SETLDS((bc_rpm_kernel<int32_t, true>))
 #undef PLUQ_SETLDS
+    hipError_t e = hipSuccess;
+#define PLUQ_SETOUT(K)                                                                                 \
+    if (e == hipSuccess)                                                                                \
+        e = hipFuncSetAttribute((const void *)(K), hipFuncAttributeMaxDynamicSharedMemorySize, BC_OUT_BYTES);
+    PLUQ_SETOUT((bc_lu_kernel<int64_t, 64, false>))
+    PLUQ_SETOUT((bc_lu_kernel<double, 64, false>))
+    PLUQ_SETOUT((bc_lu_kernel<int32_t, 64, false>))
+    PLUQ_SETOUT((bc_lu_kernel<int64_t, 128, false>))
+    PLUQ_SETOUT((bc_lu_kernel<double, 128, false>))
+    PLUQ_SETOUT((bc_lu_kernel<int32_t, 128, false>))
+#undef PLUQ_SETOUT
+    if (e != hipSuccess) return e;
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-        prop.sharedMemPerBlock < BC_TAB_BYTES + sizeof(BcShared) + 1024)
+        prop.sharedMemPerBlock < BC_TAB_BYTES + sizeof(BcBlkShared<BC_DIM>) + 1024)
         g_tab_ok = false;
     (void)hipGetLastError();
     return hipSuccess;
@@ -595,24 +731,25 @@ hipError_t launch_build_inv_table(uint16_t *tab, double p, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int TILE>
+template <int TILE, bool TAB>
 static hipError_t bc_lu_t(int dtype, void *A, int64_t lda, int m, int n, const int32_t *rmap,
                           const int32_t *cmap, int r_known, double p, int kchunk, const uint16_t *tab,
                           int32_t *status, int32_t *specfail, int32_t *errflag, hipStream_t st) {
-    const size_t lds = tab ? BC_TAB_BYTES : 0;
+    // dynamic LDS: the table of inverses, later the staged result tile
+    const size_t lds = TAB ? BC_TAB_BYTES : (size_t)BC_OUT_BYTES;
     const ModP md = make_mod(p);
     switch (dtype) {
     case DT_I64:
-        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (int64_t *)A, lda,
-                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
+        PLUQ_LAUNCH((bc_lu_kernel<int64_t, TILE, TAB>), dim3(1), dim3(TILE * 4), lds, st, (int64_t *)A, lda, m, n,
+                    rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
         break;
     case DT_F64:
-        PLUQ_LAUNCH((bc_lu_kernel<double, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (double *)A, lda,
-                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
+        PLUQ_LAUNCH((bc_lu_kernel<double, TILE, TAB>), dim3(1), dim3(TILE * 4), lds, st, (double *)A, lda, m, n,
+                    rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
         break;
     case DT_I32:
-        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE, bc_threads(TILE)>), dim3(1), dim3(bc_threads(TILE)), lds, st, (int32_t *)A, lda,
-                    m, n, rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
+        PLUQ_LAUNCH((bc_lu_kernel<int32_t, TILE, TAB>), dim3(1), dim3(TILE * 4), lds, st, (int32_t *)A, lda, m, n,
+                    rmap, cmap, r_known, md, kchunk, tab, status, specfail, errflag);
         break;
     default: return hipErrorInvalidValue;
     }
@@ -633,9 +770,10 @@ hipError_t launch_bc_lu(int dtype, void *A, int64_t lda, int m, int n, const int
         const double c = std::floor((4503599627370496.0 - 2.0 * p) / (h * h));
         kchunk = c >= 1048576.0 ? 1048576 : (c < 1.0 ? 1 : (int)c);
     }
-    if (m <= 64 && n <= 64)
-        return bc_lu_t<64>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, errflag, st);
-    return bc_lu_t<128>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, errflag, st);
+#define PLUQ_BC(TILE, TAB) bc_lu_t<TILE, TAB>(dtype, A, lda, m, n, rmap, cmap, r_known, p, kchunk, tab, status, specfail, errflag, st)
+    if (m <= 64 && n <= 64) return tab ? PLUQ_BC(64, true) : PLUQ_BC(64, false);
+    return tab ? PLUQ_BC(128, true) : PLUQ_BC(128, false);
+#undef PLUQ_BC
 }
 
 hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, double p, int kchunk,
