@@ -150,19 +150,29 @@ def test_batched_graph_replays(gpu_lib):
 
 def test_batched_workload_4096(gpu_lib):
     """The 4096-matrix workload (m, n ~ U{32..512}, r ~ U{0..min}, permuted
-    X.Y over GF(65521), int32): every rank equals the oracle's; a sample of
-    matrices is compared in full."""
-    import torch
+    X.Y over GF(65521), int32): every matrix's (r, P, Q, packed factors)
+    equals the oracle's, through the digests tests/golden/fullsize.py wrote
+    from the oracle on the same seeded matrices; a sample is also compared
+    entry by entry with the oracle run here."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "fullsize_golden", os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.py"))
+    golden = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(golden)
+    rec = golden.load()["c5_batch4096_p65521"]
     p = 65521
     mats = gen.batch_xy(4096, p, shape_seed=0, content_seed=0)
     note("batched workload 4096")
     dev, Ps, Qs, d_r = _run_batch(gpu_lib, mats, p, "int32")
     rs = d_r.cpu().numpy()
-    sample = list(range(0, 4096, 97)) + [int(np.argmax([A.size for A in mats]))]
+    assert rs.tolist() == rec["ranks"]
+    bad = []
+    for b in range(len(mats)):
+        d = golden.record_digest(int(rs[b]), Ps[b].cpu().numpy(), Qs[b].cpu().numpy(),
+                                 dev[b].cpu().numpy().astype(np.int64))
+        if d[:16] != rec["record_sha256_16"][b]:
+            bad.append(b)
+    assert not bad, f"{len(bad)} matrices differ from the oracle, first {bad[:8]}"
+    sample = list(range(0, 4096, 409)) + [int(np.argmax([A.size for A in mats]))]
     _check_against_oracle(mats, p, dev, Ps, Qs, d_r, which=sample)
-    _, _, r_nominal = gen.batch_shapes(4096, 0)
-    # ranks of all matrices: the oracle's rank of each (computed on the host)
-    ranks = [oracle.pluqz(A, p)[2] for A in mats[:512]]
-    assert np.array_equal(rs[:512], np.array(ranks))
-    assert np.all(rs >= 0)
-    assert np.mean(rs == r_nominal) > 0.99
