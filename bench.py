@@ -1,25 +1,28 @@
 """Benchmark of the rank-profile PLUQ on one MI355X.
 
-A step is one whole decomposition of each matrix of the workload (restored
-from a pristine device copy first, since the decomposition is in place); the
-two decompositions of a step run concurrently on two HIP streams.
-Default workload: 4096 x 4096 over GF(65521), two matrices per step -- a
-full-rank uniform one and a rank-2048 permuted X.Y product -- in the FP64
-matrix-core form with float64 storage.
+Headline workload (the configuration the metric is quoted on): one
+16384 x 16384 matrix of rank 12000 over GF(65521), A = X.Y mod p with X, Y
+uniform and rows and columns shuffled by seeded permutations, float64
+storage, decomposed in the INT8-limb form (large Schur updates on the int8
+matrix cores, two signed base-256 digits per residue).  A step restores A
+from a pristine device copy (in place decomposition) and decomposes it; the
+input is resident in HBM before the timed region.
 
-Metric: effective GOPS = sum over the step's matrices of 2 m n r, divided by
-the wall time of the timed steps.  Also reported: the classical-operation
-rate (2 * sum_{k<r} (m-k-1)(n-k-1) per matrix), the roofline position of the
-dominant kernel (the MM update, timed with HIP events on the library's
-stream inside the timed region), and the CPU oracle on a bounded sample.
+Metric: effective GOPS = 2 m n r per decomposition / wall time of the timed
+steps.  Also reported: the classical-operation rate (2 sum_{k<r}
+(m-k-1)(n-k-1)), the roofline position of the dominant kernel of the step
+(device time per kernel class from HIP events on the library's stream during
+the last timed step), and the CPU oracle on a bounded sample.
 
-After the timed region (and not part of `value`): the INT8-limb form on the
-same pair, the 16384 x 16384 rank-12000 workload over GF(65521) and GF(251)
-in every form, and the batch of 4096 small matrices in one persistent launch
-against per-matrix launches (`comparisons`).
+After the timed region (not part of `value`): the FP64 and FP32 forms on
+the same workload and for p = 251, the planted L.E.U companion, the
+8192 x 16384 workload with a zero leading block, the 4096 x 4096 pair, an
+isolated 8192 x 8192 x 4096 update in every form, and the batch of 4096
+small matrices as a replayed HIP graph against per-matrix launches
+(`comparisons`).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                       [--no-comparisons]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2]
+                       [--no-cpu-baseline] [--no-comparisons]
 """
 from __future__ import annotations
 
@@ -36,32 +39,38 @@ if ROOT not in sys.path:
 
 METRIC = "effective GOPS (2mnr) of PLUQ mod p, INT8-limb & batched vs plain FP64"
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
 INT8_MFMA_PEAK_TOPS = 5000.0
 HBM_PEAK_GBS = 8000.0
 
+# Roofline of each kernel class: bound, peak, unit, the kernel(s) it times.
+CLASS_ROOF = {
+    "modmm_i8": ("mfma", INT8_MFMA_PEAK_TOPS, "TOP/s", "modmm_i8_kernel (int8 limb GEMM)"),
+    "modmm": ("mfma", FP64_MFMA_PEAK_TFLOPS, "TFLOP/s", "modmm_kernel<double> (FP64 MM update)"),
+    "trsm_leaf": ("mfma", FP64_MFMA_PEAK_TFLOPS, "TFLOP/s", "trsm_leaf_pair_kernel / trsm_leaf_kernel"),
+    "trsm_diag": ("alu", FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "trsm_diag_inv_pair_kernel / trsm_diag_inv_kernel"),
+    "basecase": ("alu", FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "bc_lu_kernel (128 x 128 tile, one work-group)"),
+    "basecase_rpm": ("alu", FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s", "bc_rpm_kernel"),
+    "limb": ("hbm", HBM_PEAK_GBS, "GB/s", "limb_split_kernel"),
+    "perm": ("hbm", HBM_PEAK_GBS, "GB/s", "gather2d_kernel"),
+    "scan": ("hbm", HBM_PEAK_GBS, "GB/s", "zscan_kernel"),
+}
 
-# HBM traffic of the MM kernel per launch on this workload, from two
-# rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --no-comparisons` (FETCH_SIZE, then WRITE_SIZE).  FETCH_SIZE reads 0.5001x
-# the bytes of the plain 128 MiB device copies (restoring the inputs) in the
-# same runs and WRITE_SIZE 1.0000x, so the fetch counter is scaled by 1.9995.
-# The figures hold only for the code they were taken on: the MM kernel's
-# (k_modmm.hip + common.hpp) and the recursion's (driver.hip), which decides
-# the mix of update shapes a step launches (sha256 prefix of that code,
-# comments removed).
-MM_TRAFFIC = {"source_sha256_16": "0764e295c667efb0",
-              "fetch_bytes_per_launch": 36915.0 * 1024, "write_bytes_per_launch": 4864.15 * 1024}
+# HBM traffic per launch of a kernel class on the headline workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+# `bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-comparisons`, each
+# scaled by what the counter reads for a plain device copy of known size in
+# the same run.  Valid only for the code the counters were taken on (sha256
+# prefix of the listed sources, comments removed); empty until measured.
+TRAFFIC = {}
 
 
-def mm_source_hash() -> str:
-    """sha256 prefix of the code (comments and blank lines removed) of
-    k_modmm.hip + common.hpp + driver.hip: the counters depend on the MM
-    code and on the mix of updates the recursion launches."""
+def source_hash(files) -> str:
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("k_modmm.hip", "common.hpp", "driver.hip"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1301_4438_amd", "csrc", f), encoding="utf-8") as fh:
             for line in fh:
                 code = re.sub(r"//.*$", "", line).strip()
@@ -78,40 +87,76 @@ def classical_ops(m: int, n: int, r: int) -> float:
     return 2.0 * s
 
 
-def make_workload(name: str, seed: int):
+def make_c4(p: int, seed: int):
     import torch
     import pluq_inputs as gen
-    if name == "c2":
-        p, n = 65521, 4096
-        full = torch.from_numpy(gen.uniform(n, n, p, seed)).to(torch.float64).cuda()
-        half = gen.xy_permuted(n, n, 2048, p, seed, device="cuda").to(torch.float64)
-        desc = ("4096x4096 over GF(65521): full-rank uniform + rank-2048 permuted X.Y, "
-                "two matrices per step, FP64 matrix-core form, float64 storage")
-        return p, [full, half], desc
-    raise SystemExit(f"unknown workload {name}")
+    return gen.xy_permuted(16384, 16384, 12000, p, seed, device="cuda").to(torch.float64)
 
 
-def cpu_baseline(seed: int):
-    """The oracle on one step of the default workload (the same two seeded
-    4096 x 4096 matrices over GF(65521)), scaled to effective GOPS."""
-    import oracle
-    import pluq_inputs as gen
-    p, n = 65521, 4096
-    mats = [gen.uniform(n, n, p, seed), gen.xy_permuted(n, n, n // 2, p, seed)]
-    ops = 0.0
+def sync_all():
+    import torch
+    torch.cuda.synchronize()
+
+
+def roofline(prof: dict):
+    """The kernel class with the most device time in the profiled step, and
+    its achieved rate (algorithmic work / device time) against its peak."""
+    live = {c: v for c, v in prof.items() if v["launches"] and c in CLASS_ROOF}
+    cls = max(live, key=lambda c: live[c]["ms"])
+    v = live[cls]
+    bound, peak, unit, kernel = CLASS_ROOF[cls]
+    secs = v["ms"] * 1e-3
+    if bound == "hbm":
+        achieved = v["bytes"] / secs / 1e9
+    else:
+        achieved = v["flops"] / secs / 1e12
+    traffic = None
+    t = TRAFFIC.get(cls)
+    if t and source_hash(t["sources"]) == t["source_sha256_16"]:
+        traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+    return {"bound": bound, "class": cls, "kernel": kernel, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic, "launches": v["launches"],
+            "avg_launch_ms": v["ms"] / v["launches"], "device_ms_in_profiled_step": v["ms"],
+            "algorithmic_work_per_launch": (v["bytes"] if bound == "hbm" else v["flops"]) / v["launches"],
+            "work_unit": "bytes" if bound == "hbm" else ("int8 ops" if cls == "modmm_i8" else "flops")}
+
+
+def time_steps(pl, pristine, p, form, steps, warmup, profile_last=True):
+    """Warm-up, then `steps` timed decompositions of the matrix (restored
+    from `pristine` in each step); the last one profiled per kernel class."""
+    import torch
+    X = pristine.clone()
+    P = torch.empty(X.shape[0], dtype=torch.int64, device="cuda")
+    Q = torch.empty(X.shape[1], dtype=torch.int64, device="cuda")
+    o = pl._opts(form)
+    ws = torch.empty(max(pl.pluq_workspace_size(X.shape[0], X.shape[1], 1, p, o), 256), dtype=torch.uint8,
+                     device="cuda")
+    r = None
+    for _ in range(warmup):
+        X.copy_(pristine)
+        r = pl.pluq_modp(X, p, P, Q, o, ws)
+    sync_all()
+    prof = None
     t0 = time.perf_counter()
-    for A in mats:
-        _, _, r, _ = oracle.pluqz(A, p)
-        ops += 2.0 * n * n * r
-    dt = time.perf_counter() - t0
-    return {"value": ops / dt / 1e9, "unit": "GOPS", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"one step of the workload: 4096x4096 over GF({p}), full-rank uniform + "
-                      f"rank-2048 permuted X.Y, {dt:.1f} s"}
+    for k in range(steps):
+        X.copy_(pristine)
+        last = profile_last and k == steps - 1
+        if last:
+            pl.pluq_profile_enable(-1)
+        r = pl.pluq_modp(X, p, P, Q, o, ws)
+        if last:
+            prof = pl.pluq_profile_read()
+            pl.pluq_profile_enable(0)
+    sync_all()
+    secs = time.perf_counter() - t0
+    stats = pl.pluq_last_stats()
+    del X, ws
+    return r, secs, prof, stats
 
 
-def _time_decomp(pl, A, p, form, reps=2):
+def best_of(pl, A, p, form, reps=3):
     """Best-of-reps wall time of one in-place decomposition (input restored
-    from A before each run, outside the timing); returns (rank, seconds)."""
+    outside the timing); returns (rank, seconds)."""
     import torch
     X = A.clone()
     P = torch.empty(A.shape[0], dtype=torch.int64, device=A.device)
@@ -121,35 +166,43 @@ def _time_decomp(pl, A, p, form, reps=2):
     best = float("inf")
     for _ in range(reps):
         X.copy_(A)
-        torch.cuda.synchronize()
+        sync_all()
         t0 = time.perf_counter()
         r = pl.pluq_modp(X, p, P, Q, o)
-        torch.cuda.synchronize()
+        sync_all()
         best = min(best, time.perf_counter() - t0)
+    del X
     return r, best
 
 
-def basecase_figures(bc, n):
-    """Base-case kernel figures from the profiled step: average launch time,
-    time per pivot of a full 128 x 128 tile, and its algorithmic work
-    (2/3 t^3 flops of an LU of a t x t tile) against one compute unit's share
-    of the FP64 peak (the kernel runs on one work-group by design)."""
-    if not bc or not bc["launches"]:
-        return None
-    t = 128
-    ms = bc["ms"] / bc["launches"]
-    flops = 2.0 / 3.0 * t ** 3
-    gflops = flops / (ms * 1e-3) / 1e9
-    cu_peak_gflops = FP64_MFMA_PEAK_TFLOPS * 1e3 / 256
-    return {"kernel": "bc_lu (128 x 128 tile, 512 threads, one work-group)", "bound": "latency",
-            "launches": bc["launches"], "avg_launch_ms": ms, "us_per_pivot": ms * 1e3 / t,
-            "algorithmic_flops_per_launch": flops, "achieved_gflops": gflops,
-            "one_cu_fp64_peak_gflops": cu_peak_gflops, "frac_of_one_cu": gflops / cu_peak_gflops}
+def form_record(m, n, r, secs, form):
+    eff = 2.0 * m * n * r / secs
+    rec = {"ms": secs * 1e3, "gops": eff / 1e9, "rank": r}
+    if form == "fp64":
+        rec["frac_of_fp64_peak_2mnr"] = eff / 1e12 / FP64_MFMA_PEAK_TFLOPS
+    elif form == "fp32":
+        rec["frac_of_fp32_peak_2mnr"] = eff / 1e12 / FP32_MFMA_PEAK_TFLOPS
+    return rec
+
+
+def cpu_baseline(A_dev):
+    """The oracle on the leading 4096 x 4096 block of the benchmark's input
+    (the same workload, bounded to some 10-30 s of CPU work)."""
+    import numpy as np
+    import oracle
+    p = 65521
+    S = np.ascontiguousarray(A_dev[:4096, :4096].to(dtype=A_dev.dtype).cpu().numpy().astype(np.int64))
+    t0 = time.perf_counter()
+    _, _, r, _ = oracle.pluqz(S, p)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * 4096 * 4096 * r / dt / 1e9, "unit": "GOPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"the leading 4096 x 4096 block of the benchmark's 16384 x 16384 input over GF(65521) "
+                      f"(rank {r}), {dt:.1f} s"}
 
 
 def large_update(pl, seed):
-    """One large update on its own, 8192 x 8192 x 4096 (one INT8 launch
-    deep), in every form: time per call and the fraction of the form's peak."""
+    """One large update on its own, 8192 x 8192 x 4096, in every form: time
+    per call and the fraction of the form's peak."""
     import torch
     mmr = {}
     g = torch.Generator(device="cuda").manual_seed(seed)
@@ -158,12 +211,14 @@ def large_update(pl, seed):
         Aop = torch.randint(0, p, (8192, 4096), device="cuda", generator=g, dtype=torch.int64).to(torch.float64)
         Bop = torch.randint(0, p, (4096, 8192), device="cuda", generator=g, dtype=torch.int64).to(torch.float64)
         pl.pluq_modmm(C, Aop, Bop, p, form=form)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True); e1 = torch.cuda.Event(enable_timing=True)
+        sync_all()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(3):
             pl.pluq_modmm(C, Aop, Bop, p, form=form)
-        e1.record(); torch.cuda.synchronize()
+        e1.record()
+        sync_all()
         ms = e0.elapsed_time(e1) / 3
         tf = 2.0 * 8192 * 8192 * 4096 / (ms * 1e-3) / 1e12
         rec = {"ms": ms, "tflops_2mnk": tf}
@@ -182,89 +237,153 @@ def large_update(pl, seed):
     return mmr
 
 
-def comparisons(pl, c2_pristine, seed):
-    """The other forms and workloads, measured after the timed region: the
-    INT8-limb form on the same 4096 pair; the 16384 x 16384 rank-12000
-    permuted X.Y over GF(65521) and GF(251) in every form; the batch of 4096
-    matrices (m, n ~ U{32..512}, r ~ U{0..min}) in one persistent launch
-    against per-matrix plain launches."""
+def c2_pair(pl, seed):
+    """The 4096 x 4096 pair over GF(65521) (full-rank uniform + rank-2048
+    permuted X.Y) in the FP64 form, the two decompositions of a step on two
+    HIP streams from two host threads, and the planted rank-2048 companion."""
+    import torch
+    import pluq_inputs as gen
+    p, n = 65521, 4096
+    mats = [torch.from_numpy(gen.uniform(n, n, p, seed)).to(torch.float64).cuda(),
+            gen.xy_permuted(n, n, 2048, p, seed, device="cuda").to(torch.float64)]
+    work = [a.clone() for a in mats]
+    Ps = [torch.empty(n, dtype=torch.int64, device="cuda") for _ in mats]
+    Qs = [torch.empty(n, dtype=torch.int64, device="cuda") for _ in mats]
+    o = pl._opts("fp64")
+    streams = [torch.cuda.Stream() for _ in mats]
+    wss = [torch.empty(pl.pluq_workspace_size(n, n, 1, p, o), dtype=torch.uint8, device="cuda") for _ in mats]
+    pool = ThreadPoolExecutor(max_workers=2)
+
+    def one(i):
+        with torch.cuda.stream(streams[i]):
+            work[i].copy_(mats[i])
+            return pl.pluq_modp(work[i], p, Ps[i], Qs[i], o, wss[i])
+
+    def step():
+        return [f.result() for f in [pool.submit(one, i) for i in range(2)]]
+
+    for _ in range(3):
+        step()
+    sync_all()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ranks = step()
+    sync_all()
+    secs = (time.perf_counter() - t0) / reps
+    pool.shutdown()
+    ops = sum(2.0 * n * n * r for r in ranks)
+    out = {"fp64_two_streams": {"ms_per_step": secs * 1e3, "gops": ops / secs / 1e9, "ranks": ranks}}
+    secs8 = 0.0
+    for A in mats:
+        _, t = best_of(pl, A, p, "int8")
+        secs8 += t
+    out["int8_sequential"] = {"ms_per_step": secs8 * 1e3, "gops": ops / secs8 / 1e9}
+    A, _ = gen.planted_leu(n, n, 2048, p, seed + 1, device="cuda")
+    A = A.to(torch.float64)
+    r, t = best_of(pl, A, p, "fp64")
+    out["planted_r2048_fp64"] = form_record(n, n, r, t, "fp64")
+    r8, t8 = best_of(pl, A, p, "int8")
+    out["planted_r2048_int8"] = form_record(n, n, r8, t8, "int8")
+    return out
+
+
+def c5_batch(pl, seed):
+    """The batch of 4096 matrices over GF(65521) (m, n ~ U{32..512},
+    r ~ U{0..min(m, n)}, permuted X.Y, int32 storage) decomposed by one
+    persistent launch captured into a HIP graph and replayed, against one
+    plain decomposition call per matrix."""
     import numpy as np
     import torch
     import pluq_inputs as gen
-    out = {}
-    # INT8 form on the benchmark pair
-    secs, ops = 0.0, 0.0
-    for A in c2_pristine:
-        r, t = _time_decomp(pl, A, 65521, "int8")
-        secs += t
-        ops += 2.0 * A.shape[0] * A.shape[1] * r
-    out["c2_4096_pair_int8"] = {"ms_per_step": secs * 1e3, "gops": ops / secs / 1e9,
-                                "note": "the two decompositions one after the other"}
-    # its counterpart: the FP64 form, also one after the other
-    secs64 = 0.0
-    for A in c2_pristine:
-        _, t = _time_decomp(pl, A, 65521, "fp64")
-        secs64 += t
-    out["c2_4096_pair_fp64_sequential"] = {"ms_per_step": secs64 * 1e3, "gops": ops / secs64 / 1e9}
-    # 16384^2 rank 12000, every form; MM-kernel rate of the INT8 form
-    for p, forms in [(65521, ["fp64", "int8"]), (251, ["fp64", "int8", "fp32"])]:
-        A = gen.xy_permuted(16384, 16384, 12000, p, seed, device="cuda").to(torch.float64)
-        rec = {}
-        for f in forms:
-            r, t = _time_decomp(pl, A, p, f)
-            rec[f] = {"ms": t * 1e3, "gops": 2.0 * 16384 * 16384 * r / t / 1e9, "rank": r}
-        # one more INT8 run with the MM launches timed
-        X = A.clone()
-        P = torch.empty(16384, dtype=torch.int64, device="cuda")
-        Q = torch.empty(16384, dtype=torch.int64, device="cuda")
-        pl.pluq_profile_enable((1 << 0) | (1 << 5))
-        pl.pluq_modp(X, p, P, Q, pl._opts("int8"))
-        prof = pl.pluq_profile_read()
-        pl.pluq_profile_enable(0)
-        mm, lb = prof["modmm"], prof["limb"]
-        nl = 1 if p <= 256 else 2
-        rec["int8_mm_kernels"] = {
-            "mm_launches": mm["launches"], "mm_ms": mm["ms"], "split_ms": lb["ms"],
-            "tflops_2mnk": mm["flops"] / (mm["ms"] * 1e-3) / 1e12 if mm["ms"] else 0.0,
-            "note": f"MM launches of one INT8-form decomposition (large updates on int8 matrix cores, "
-                    f"{nl * nl} limb products per multiply-add; small ones in the FP64 kernel)"}
-        rec["speedup_int8_vs_fp64"] = rec["fp64"]["ms"] / rec["int8"]["ms"]
-        out[f"c4_16384_r12000_p{p}"] = rec
-        del A, X
-        torch.cuda.empty_cache()
-    out["mm_8192x8192x4096"] = large_update(pl, seed)
-    # batched form: 4096 matrices, int32 storage, GF(65521)
     p = 65521
     m, n, r = gen.batch_shapes(4096, seed)
-    pristine = [gen.xy_permuted(int(m[i]), int(n[i]), int(r[i]), p, seed * 1_000_003 + i, device="cuda")
-                .to(torch.int32).contiguous() for i in range(4096)]
-    dev = [t.clone() for t in pristine]
-    Ps = [torch.empty(t.shape[0], dtype=torch.int64, device="cuda") for t in pristine]
-    Qs = [torch.empty(t.shape[1], dtype=torch.int64, device="cuda") for t in pristine]
+    sizes = (m * n).astype(np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    flat0 = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    for i in range(4096):
+        A = gen.xy_permuted(int(m[i]), int(n[i]), int(r[i]), p, seed * 1_000_003 + i, device="cuda")
+        flat0[int(offs[i]):int(offs[i + 1])].copy_(A.reshape(-1).to(torch.int32))
+    flat = flat0.clone()
+    dev = [flat[int(offs[i]):int(offs[i + 1])].view(int(m[i]), int(n[i])) for i in range(4096)]
+    Ps = [torch.empty(int(x), dtype=torch.int64, device="cuda") for x in m]
+    Qs = [torch.empty(int(x), dtype=torch.int64, device="cuda") for x in n]
     d_r = torch.empty(4096, dtype=torch.int64, device="cuda")
     call = pl.BatchedCall(dev, p, Ps, Qs, d_r).prepare()
-    best = float("inf")
-    for _ in range(3):
-        for t, s0 in zip(dev, pristine):
-            t.copy_(s0)
-        torch.cuda.synchronize()
+    sync_all()
+    side = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        call.run(stream=torch.cuda.current_stream().cuda_stream)
+    sync_all()
+    times = []
+    for _ in range(5):
+        flat.copy_(flat0)
+        sync_all()
         t0 = time.perf_counter()
-        call.run()
-        torch.cuda.synchronize()
-        best = min(best, time.perf_counter() - t0)
+        graph.replay()
+        sync_all()
+        times.append(time.perf_counter() - t0)
+    best = min(times)
     ranks = d_r.cpu().numpy()
     ops = float(np.sum(2.0 * m * n * ranks))
-    for t, s0 in zip(dev, pristine):
-        t.copy_(s0)
-    torch.cuda.synchronize()
+    flat.copy_(flat0)
+    sync_all()
     t0 = time.perf_counter()
     for i in range(4096):
         pl.pluq_modp(dev[i], p, Ps[i], Qs[i])
-    torch.cuda.synchronize()
+    sync_all()
     plain = time.perf_counter() - t0
-    out["c5_batch4096"] = {"batched_ms": best * 1e3, "batched_gops": ops / best / 1e9,
-                           "per_matrix_plain_ms": plain * 1e3, "per_matrix_plain_gops": ops / plain / 1e9,
-                           "speedup_batched_vs_plain": plain / best, "failed_self_checks": int(np.sum(ranks < 0))}
+    return {"batched_graph_replay_ms": best * 1e3, "batched_gops": ops / best / 1e9,
+            "replays": len(times), "median_replay_ms": float(np.median(times)) * 1e3,
+            "per_matrix_plain_ms": plain * 1e3, "per_matrix_plain_gops": ops / plain / 1e9,
+            "speedup_batched_vs_plain": plain / best, "failed_self_checks": int(np.sum(ranks < 0)),
+            "sum_2mnr": ops}
+
+
+def comparisons(pl, A65521, seed):
+    import torch
+    import pluq_inputs as gen
+    out = {}
+    n = 16384
+    # the headline matrix in the FP64 form
+    rec = {}
+    r, t = best_of(pl, A65521, 65521, "fp64")
+    rec["fp64"] = form_record(n, n, r, t, "fp64")
+    r, t = best_of(pl, A65521, 65521, "int8")
+    rec["int8"] = form_record(n, n, r, t, "int8")
+    rec["speedup_int8_vs_fp64"] = rec["fp64"]["ms"] / rec["int8"]["ms"]
+    out["c4_16384_r12000_p65521"] = rec
+    # p = 251: FP64, INT8 (one limb), FP32
+    A = make_c4(251, seed)
+    rec = {}
+    for f in ("fp64", "int8", "fp32"):
+        r, t = best_of(pl, A, 251, f)
+        rec[f] = form_record(n, n, r, t, f)
+    rec["speedup_int8_vs_fp64"] = rec["fp64"]["ms"] / rec["int8"]["ms"]
+    rec["speedup_fp32_vs_fp64"] = rec["fp64"]["ms"] / rec["fp32"]["ms"]
+    out["c4_16384_r12000_p251"] = rec
+    del A
+    torch.cuda.empty_cache()
+    # planted L.E.U companion (rank profile matrix off the diagonal)
+    A, _ = gen.planted_leu(n, n, 12000, 65521, seed + 1, device="cuda")
+    A = A.to(torch.float64)
+    rec = {}
+    for f in ("fp64", "int8"):
+        r, t = best_of(pl, A, 65521, f, reps=2)
+        rec[f] = form_record(n, n, r, t, f)
+    out["c4planted_16384_r12000_p65521"] = rec
+    del A
+    torch.cuda.empty_cache()
+    # 8192 x 16384, rank 4096, leading 512 x 512 zero block, GF(8388593)
+    A = gen.zero_block(8192, 16384, 4096, 512, 8388593, seed, device="cuda").to(torch.float64)
+    r, t = best_of(pl, A, 8388593, "fp64", reps=2)
+    out["c3_8192x16384_r4096_z512_p8388593"] = {"fp64": form_record(8192, 16384, r, t, "fp64")}
+    del A
+    torch.cuda.empty_cache()
+    out["c2_4096_pair_p65521"] = c2_pair(pl, seed)
+    out["mm_8192x8192x4096"] = large_update(pl, seed)
+    out["c5_batch4096_p65521"] = c5_batch(pl, seed)
     return out
 
 
@@ -273,7 +392,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c4", choices=["c4", "c2"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparisons", action="store_true",
@@ -282,73 +401,24 @@ def main():
                     help="time only the 8192 x 8192 x 4096 update in every form (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: this library runs on one GPU; --gpus must be 1 (no multi-GPU path is built)",
+              file=sys.stderr)
         sys.exit(2)
 
-    import torch
     import paper_1301_4438_amd as pl
     pl.load()
     if args.only_mm:
         print(json.dumps({"mm_8192x8192x4096": large_update(pl, args.seed)}), flush=True)
         return
-    p, pristine, desc = make_workload(args.workload, args.seed)
-    work = [a.clone() for a in pristine]
-    Ps = [torch.empty(a.shape[0], dtype=torch.int64, device="cuda") for a in pristine]
-    Qs = [torch.empty(a.shape[1], dtype=torch.int64, device="cuda") for a in pristine]
-    opts = pl._opts("fp64")
-    # The matrices of a step are independent decompositions: each runs on its
-    # own HIP stream from its own host thread (the library keeps its host
-    # state per thread), with its own workspace, so that one decomposition's
-    # latency-bound stretches (base cases, small updates, rank readbacks)
-    # overlap with the other's work.
-    streams = [torch.cuda.Stream() for _ in pristine]
-    wss = [torch.empty(max(pl.pluq_workspace_size(a.shape[0], a.shape[1], 1, p, opts), 256),
-                       dtype=torch.uint8, device="cuda") for a in pristine]
-    pool = ThreadPoolExecutor(max_workers=len(pristine))
+    if args.workload == "c2":
+        print(json.dumps(c2_pair(pl, args.seed)), flush=True)
+        return
 
-    def one(i, profile):
-        with torch.cuda.stream(streams[i]):
-            if profile:
-                pl.pluq_profile_enable(-1)   # every kernel class, last step only
-            work[i].copy_(pristine[i])
-            r = pl.pluq_modp(work[i], p, Ps[i], Qs[i], opts, wss[i])
-            prof = pl.pluq_profile_read() if profile else None
-            if profile:
-                pl.pluq_profile_enable(0)
-            return r, prof, pl.pluq_last_stats()
-
-    def step(profile=False):
-        return [f.result() for f in [pool.submit(one, i, profile) for i in range(len(work))]]
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    # The launches of the last timed step are timed one by one with events
-    # attached to their dispatches; attaching them costs a few microseconds of
-    # launch latency each, so the other steps run without them.
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        res = step(profile=(k == args.steps - 1))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pool.shutdown()
-    ranks = [r for r, _, _ in res]
-    prof = {}
-    for _, pr, _ in res:
-        for c, v in pr.items():
-            acc = prof.setdefault(c, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
-            for key in acc:
-                acc[key] += v[key]
-    stats = res[-1][2]
-
-    secs = t1 - t0
-    eff_ops = sum(2.0 * a.shape[0] * a.shape[1] * r for a, r in zip(pristine, ranks)) * args.steps
-    cls_ops = sum(classical_ops(a.shape[0], a.shape[1], r) for a, r in zip(pristine, ranks)) * args.steps
-    mm = prof["modmm"]
-    achieved = mm["flops"] / (mm["ms"] * 1e-3) / 1e12 if mm["ms"] > 0 else 0.0
-    traffic = None
-    if mm_source_hash() == MM_TRAFFIC["source_sha256_16"]:
-        traffic = MM_TRAFFIC["fetch_bytes_per_launch"] + MM_TRAFFIC["write_bytes_per_launch"]
+    p, m, n = 65521, 16384, 16384
+    A = make_c4(p, args.seed)
+    r, secs, prof, stats = time_steps(pl, A, p, "int8", args.steps, args.warmup)
+    eff_ops = 2.0 * m * n * r * args.steps
+    cls_ops = classical_ops(m, n, r) * args.steps
     out = {
         "metric": METRIC,
         "value": eff_ops / secs / 1e9,
@@ -360,33 +430,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "int8+f64",
         "data": "synthetic",
-        "config": {"workload": desc, "m": pristine[0].shape[0], "n": pristine[0].shape[1], "p": p,
-                   "ranks": ranks, "form": "fp64", "storage": "float64",
-                   "concurrency": "the two decompositions of a step on two HIP streams"},
+        "config": {"workload": "16384x16384 rank-12000 permuted X.Y over GF(65521), INT8-limb form "
+                               "(two signed base-256 digits, int8 matrix cores), float64 storage, "
+                               "one decomposition per step (input restored from an HBM copy)",
+                   "m": m, "n": n, "r": r, "p": p, "form": "int8", "storage": "float64"},
         "classical_gops": cls_ops / secs / 1e9,
-        "roofline": {"bound": "mfma", "kernel": "modmm_f64", "achieved": achieved,
-                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                     "launches": mm["launches"], "avg_launch_ms": mm["ms"] / max(mm["launches"], 1),
-                     "mm_ms_in_profiled_step": mm["ms"],
-                     "profiled_steps": 1,
-                     "algorithmic_bytes_per_launch": mm["bytes"] / max(mm["launches"], 1),
-                     "traffic": traffic},
-        # By device time the base case is the largest single kernel: one
-        # work-group per 128 x 128 tile (one compute unit), its pivots in
-        # sequence, so it is bound by the latency of each pivot's exchange,
-        # not by a throughput roof; its figures per launch and per pivot.
-        "latency_bound_basecase": basecase_figures(prof.get("basecase"), pristine[0].shape[0]),
+        "frac_of_int8_peak_2mnr_x4": eff_ops / secs / 1e12 * 4 / INT8_MFMA_PEAK_TOPS,
+        "frac_of_fp64_peak_2mnr": eff_ops / secs / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+        "roofline": roofline(prof),
         "device_ms_per_class_in_profiled_step": {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]},
         "launches_per_class_in_profiled_step": {c: v["launches"] for c, v in prof.items() if v["launches"]},
         "library_stats_last_call": stats,
     }
     if not args.no_comparisons:
-        out["comparisons"] = comparisons(pl, pristine, args.seed)
+        out["comparisons"] = comparisons(pl, A, args.seed)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.seed)
+        out["cpu_baseline"] = cpu_baseline(A)
     print(json.dumps(out), flush=True)
 
 

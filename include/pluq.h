@@ -105,6 +105,11 @@ const char *pluq_status_string(pluq_status s);
 /* Library version string (static storage). */
 const char *pluq_version(void);
 
+/* Detail of the last failure on the calling thread (which HIP call or host
+ * allocation failed, and its error string); "" if none.  Thread-local
+ * storage, valid until the thread's next failing call. */
+const char *pluq_last_error(void);
+
 /*
  * Device workspace, in bytes, needed by pluq_modp for an m x n matrix of the
  * given element type, modulus and options (opts may be NULL for defaults).
@@ -252,8 +257,10 @@ void pluq_last_stats(int64_t *nodes, int64_t *basecases, int64_t *launches,
  * kernel launch of pluq_modp is bracketed by HIP events on the caller's
  * stream and, per class, the launch count, the summed device time and the
  * algorithmic work are accumulated:
- *   flops -- 2 * M * N * K of each matrix-multiply update (the classical
- *            multiply-add count), 0 for the other classes;
+ *   flops -- 2 * M * N * K of each matrix-multiply update (twice the
+ *            classical multiply-add count; for PLUQ_K_MODMM_I8 times the
+ *            limb products per multiply-add, i.e. int8 operations), the
+ *            matrix-core work of the solve leaves, 0 for the other classes;
  *   bytes -- compulsory HBM traffic of the launch (operands read once,
  *            outputs read and written once).
  * pluq_profile_enable(mask) resets the counters and records the classes
@@ -269,7 +276,10 @@ enum {
     PLUQ_K_BASECASE = 3,  /* base-case tiles */
     PLUQ_K_SCAN = 4,      /* zero / range scans */
     PLUQ_K_LIMB = 5,      /* INT8 form: digit-plane split of MM operands */
-    PLUQ_K_COUNT = 6
+    PLUQ_K_MODMM_I8 = 6,  /* INT8 form: limb GEMMs of the large MM updates */
+    PLUQ_K_TRSM_DIAG = 7, /* triangular solves: inversion of the 64 x 64 diagonal blocks */
+    PLUQ_K_BASECASE_RPM = 8, /* base case: rank-profile search of a non-generic tile */
+    PLUQ_K_COUNT = 9
 };
 typedef struct {
     int64_t launches;

@@ -50,7 +50,8 @@ class pluq_kernel_stat(ctypes.Structure):
                 ("bytes", ctypes.c_double)]
 
 
-KERNEL_CLASSES = ["modmm", "trsm_leaf", "perm", "basecase", "scan", "limb"]
+KERNEL_CLASSES = ["modmm", "trsm_leaf", "perm", "basecase", "scan", "limb", "modmm_i8", "trsm_diag",
+                  "basecase_rpm"]
 
 
 def load():
@@ -60,10 +61,16 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_1301_4438_amd/build.py")
+    # torch first: the library must bind to the HIP runtime torch has loaded
+    # (loaded before torch, it would bring in a second runtime, and the one
+    # it calls then sees no device)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.pluq_status_string.restype = ctypes.c_char_p
     L.pluq_status_string.argtypes = [ctypes.c_int]
     L.pluq_version.restype = ctypes.c_char_p
+    L.pluq_last_error.restype = ctypes.c_char_p
+    L.pluq_last_error.argtypes = []
     L.pluq_workspace_size.restype = ctypes.c_size_t
     L.pluq_workspace_size.argtypes = [_i64, _i64, ctypes.c_int, _u64, ctypes.POINTER(pluq_opts)]
     L.pluq_modp.restype = ctypes.c_int
@@ -144,7 +151,8 @@ def _opts(form="fp64", validate=False, cutoff=0, batch_panel=0, batch_groups=0, 
 
 def _check(st, where):
     if st != PLUQ_OK:
-        raise PluqError(st, where)
+        detail = _lib.pluq_last_error().decode() if _lib is not None else ""
+        raise PluqError(st, f"{where} [{detail}]" if detail else where)
 
 
 # Workspace buffers kept between calls, per host thread and device: calls

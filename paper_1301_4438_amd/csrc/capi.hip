@@ -2,6 +2,7 @@
 // workspace carving, pinned host staging, and the top-level call of the
 // recursion driver.
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -71,9 +72,18 @@ struct Pinned {
 
 thread_local Pinned g_pin;
 
+// Detail of the last failure on this thread (pluq_last_error).
+thread_local char g_err[256] = "";
+
+void set_err(const char *where, hipError_t e) {
+    std::snprintf(g_err, sizeof(g_err), "%s: %s", where, e == hipSuccess ? "failed" : hipGetErrorString(e));
+}
+
 bool ensure_pinned(size_t idx_elems, size_t pq_elems) {
     if (!g_pin.stat) {
-        if (hipHostMalloc((void **)&g_pin.stat, STAT_WORDS * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        const hipError_t e = hipHostMalloc((void **)&g_pin.stat, STAT_WORDS * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_err("hipHostMalloc (status words)", e);
             g_pin.stat = nullptr;
             return false;
         }
@@ -88,16 +98,22 @@ bool ensure_pinned(size_t idx_elems, size_t pq_elems) {
         if (g_pin.idx) (void)hipHostFree(g_pin.idx);
         g_pin.idx = nullptr;
         g_pin.idx_cap = 0;
-        if (hipHostMalloc((void **)&g_pin.idx, idx_elems * sizeof(int32_t), hipHostMallocDefault) != hipSuccess)
+        const hipError_t e = hipHostMalloc((void **)&g_pin.idx, idx_elems * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_err("hipHostMalloc (index staging)", e);
             return false;
+        }
         g_pin.idx_cap = idx_elems;
     }
     if (g_pin.pq_cap < pq_elems) {
         if (g_pin.pq) (void)hipHostFree(g_pin.pq);
         g_pin.pq = nullptr;
         g_pin.pq_cap = 0;
-        if (hipHostMalloc((void **)&g_pin.pq, pq_elems * sizeof(int64_t), hipHostMallocDefault) != hipSuccess)
+        const hipError_t e = hipHostMalloc((void **)&g_pin.pq, pq_elems * sizeof(int64_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            set_err("hipHostMalloc (permutation staging)", e);
             return false;
+        }
         g_pin.pq_cap = pq_elems;
     }
     return true;
@@ -189,7 +205,9 @@ const char *pluq_status_string(pluq_status s) {
     return "unknown status";
 }
 
-const char *pluq_version(void) { return "pluq-mi355x 0.1 (gfx950)"; }
+const char *pluq_version(void) { return "pluq-mi355x 0.2 (gfx950)"; }
+
+const char *pluq_last_error(void) { return g_err; }
 
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
@@ -316,10 +334,12 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         *r_out = r;
         stats = c.stats;
         g_prof.resolve();
-    } catch (const DeviceError &) {
+    } catch (const DeviceError &e) {
+        set_err("pluq_modp: HIP call", e.e);
         g_prof.discard();
         return PLUQ_ERR_DEVICE;
     } catch (const std::bad_alloc &) {
+        set_err("pluq_modp: host allocation (std::bad_alloc)", hipSuccess);
         g_prof.discard();
         return PLUQ_ERR_NOMEM;
     }

@@ -271,7 +271,7 @@ bool Ctx::mm_i8(const MMProblem &pb) {
         const int8_t *pa[2] = {a0, a1}, *pbp[2] = {b0, b1};
         const double flops = 2.0 * (double)M * (double)N * (double)klen;
         const double bytes = 2.0 * M * N * (double)esz + (double)(M + N) * (double)kp * nl;
-        launch(K_MODMM, flops, bytes, [&] {
+        launch(K_MODMM_I8, flops * nl * nl, bytes, [&] {
             return launch_modmm_i8(dt, pb.C, pb.ldc, (int)M, (int)N, (int)kp, pa, pbp, kp, kp, (double)p,
                                    last ? pb.nzflag : nullptr, pb.nzgen, st);
         });
@@ -314,7 +314,7 @@ static int64_t trsm_split(int64_t r) {
 // the inverted diagonal blocks, one work-group per strip of right-hand sides).
 void Ctx::trsm_llu_p(const char *L, int64_t ldl, int64_t r, char *B, int64_t ldb, int64_t ncols) {
     if (r <= 0 || ncols <= 0) return;
-    launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 2,
+    launch(K_TRSM_DIAG, (double)r * TRSM_NB * TRSM_NB / 3.0, (double)r * TRSM_NB * esz * 2,
            [&] { return launch_trsm_diag_inv(dt, 0, L, ldl, r, trsm_w, (double)p, kchunk, st); });
     trsm_llu_rec(L, ldl, r, B, ldb, ncols, 0);
 }
@@ -338,7 +338,7 @@ void Ctx::trsm_llu_rec(const char *L, int64_t ldl, int64_t r, char *B, int64_t l
 // with non-zero diagonal; same scheme, the leaf solving the transposed system.
 void Ctx::trsm_run_p(char *B, int64_t ldb, int64_t nrows, const char *U, int64_t ldu, int64_t r) {
     if (r <= 0 || nrows <= 0) return;
-    launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 2,
+    launch(K_TRSM_DIAG, (double)r * TRSM_NB * TRSM_NB / 3.0, (double)r * TRSM_NB * esz * 2,
            [&] { return launch_trsm_diag_inv(dt, 1, U, ldu, r, trsm_w, (double)p, kchunk, st); });
     trsm_run_rec(B, ldb, nrows, U, ldu, r, 0);
 }
@@ -372,7 +372,7 @@ void Ctx::trsm_pair(int64_t ti, int64_t tj, int64_t r, int64_t di, int64_t dj, i
         return;
     }
     const char *T = at(ti, tj);
-    launch(K_TRSM, 0, (double)r * TRSM_NB * esz * 4, [&] {
+    launch(K_TRSM_DIAG, 2.0 * r * TRSM_NB * TRSM_NB / 3.0, (double)r * TRSM_NB * esz * 4, [&] {
         return launch_trsm_diag_inv_pair(dt, T, lda, T, lda, r, trsm_w, trsm_w2, (double)p, kchunk, st);
     });
     trsm_pair_rec(T, r, at(di, dj), at(ei, ej), ncols, nrows, 0);
@@ -480,12 +480,22 @@ void zorder_from_rpm(int64_t m, int64_t n, const int32_t *rpm_col_in, std::vecto
         if (!colp[j]) pcol.push_back((int32_t)j);
 }
 
+// Algorithmic flops of eliminating an m x n tile through all min(m, n)
+// steps: per step k, the (m-k-1)(n-k-1) multiply-adds of the update and the
+// m-k-1 multipliers.
+static double bc_flops(int64_t m, int64_t n) {
+    double f = 0;
+    for (int64_t k = 0; k < std::min(m, n); ++k) f += 2.0 * (double)(m - k - 1) * (double)(n - k - 1) + (double)(m - k - 1);
+    return f;
+}
+
 int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<int32_t> &prow,
                       std::vector<int32_t> &pcol) {
     stats.basecases++;
+    const double bflops = bc_flops(m, n);
     if (spec) {
         // full rank in the identity order assumed; checked later
-        launch(K_BASE, 0, 2.0 * m * n * esz, [&] {
+        launch(K_BASE, bflops, 2.0 * m * n * esz, [&] {
             return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table,
                                 d_stat + STAT_BC, d_stat + STAT_SPEC, nullptr, st);
         });
@@ -496,7 +506,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     // optimistic: the identity order (generic rank profile)
     const double tbytes = 2.0 * m * n * esz;
     if (opt_fails < 2) {
-        launch(K_BASE, 0, tbytes, [&] {
+        launch(K_BASE, bflops, tbytes, [&] {
             return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, nullptr, nullptr, -1, (double)p, kchunk, inv_table,
                                 d_stat + STAT_BC, nullptr, nullptr, st);
         });
@@ -510,7 +520,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
         ++opt_fails;
     }
     // general: rank profile matrix, then the pivot order, then the ordered LU
-    launch(K_BASE, 0, 1.0 * m * n * esz,
+    launch(K_BASE_RPM, bflops, 1.0 * m * n * esz,
            [&] { return launch_bc_rpm(dt, at(gi, gj), lda, (int)m, (int)n, (double)p, kchunk, inv_table, d_stat + STAT_BC, st); });
     read_status(STAT_BC, 1 + m);
     const int64_t r = h_stat[STAT_BC];
@@ -530,7 +540,7 @@ int64_t Ctx::basecase(int64_t gi, int64_t gj, int64_t m, int64_t n, std::vector<
     // The ordered elimination checks itself (r non-zero pivots, zero
     // remainder) into the sticky error flag, which the host reads with the
     // next read-back and at the end instead of waiting for it here.
-    launch(K_BASE, 0, tbytes, [&] {
+    launch(K_BASE, bflops, tbytes, [&] {
         return launch_bc_lu(dt, at(gi, gj), lda, (int)m, (int)n, drow, dcol, (int)r, (double)p, kchunk, inv_table,
                             d_stat + STAT_BC, nullptr, d_stat + STAT_ERR, st);
     });

@@ -23,8 +23,11 @@ struct Stats {
 extern thread_local Stats g_last_stats;
 
 // Per-kernel-class device timing (HIP events), per host thread.
-constexpr int KCLASSES = 6;
-enum KClass { K_MODMM = 0, K_TRSM = 1, K_PERM = 2, K_BASE = 3, K_SCAN = 4, K_LIMB = 5 };
+constexpr int KCLASSES = 9;
+enum KClass {
+    K_MODMM = 0, K_TRSM = 1, K_PERM = 2, K_BASE = 3, K_SCAN = 4, K_LIMB = 5, K_MODMM_I8 = 6, K_TRSM_DIAG = 7,
+    K_BASE_RPM = 8
+};
 struct KStat {
     int64_t launches = 0;
     double ms = 0, flops = 0, bytes = 0;
