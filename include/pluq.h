@@ -229,6 +229,25 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
                        size_t work_bytes, void *stream);
 
 /*
+ * pluq_modmm without a workspace argument and without allocating anything,
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, semantics and results as pluq_modmm.  In the INT8 form the
+ * digit planes go to a static 64 MiB device array of the library (one per
+ * device, held until the process ends), so m + n may be at most 1048576 for
+ * p <= 256 (one digit) and 524288 for larger p (two digits), else
+ * PLUQ_ERR_WORKSPACE with the limit in pluq_last_error(); the other forms
+ * use no scratch.  All calls on
+ * one device share that array: calls that overlap on one device (on
+ * different streams or threads) race and must be ordered by the caller.
+ * Asynchronous on `stream`; the first call on a device looks the array's
+ * address up once (hipGetSymbolAddress).
+ */
+pluq_status pluq_modmm_noalloc(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
+                               const void *dA, int64_t lda, const void *dB, int64_t ldb,
+                               pluq_dtype dt, uint64_t p, int32_t form, void *stream);
+
+/*
  * TRSM of Section 2 (device, row-major, canonical residues, asynchronous):
  *   side = 0: B <- L^{-1} B, L r x r unit lower triangular (its diagonal and
  *             upper part are not read), B r x ncols;

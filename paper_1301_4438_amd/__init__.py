@@ -97,6 +97,9 @@ def load():
     L.pluq_modmm.restype = ctypes.c_int
     L.pluq_modmm.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                              ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    L.pluq_modmm_noalloc.restype = ctypes.c_int
+    L.pluq_modmm_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
+                                     ctypes.c_int32, _vp]
     L.pluq_trsm_workspace_size.restype = ctypes.c_size_t
     L.pluq_trsm_workspace_size.argtypes = [_i64, ctypes.c_int]
     L.pluq_trsm.restype = ctypes.c_int
@@ -331,6 +334,25 @@ def pluq_modmm(C, A, B, p: int, form="fp64", work=None):
                       ctypes.c_void_p(work.data_ptr() if work is not None else 0),
                       work.numel() if work is not None else 0, _stream(C))
     _check(st, "pluq_modmm")
+
+
+def pluq_modmm_noalloc(C, A, B, p: int, form="fp64"):
+    """pluq_modmm through the entry point that allocates nothing (the INT8
+    form's digit planes in the library's static device scratch)."""
+    L = load()
+    m, n = C.shape
+    k = A.shape[1]
+    if tuple(A.shape) != (m, k) or tuple(B.shape) != (k, n):
+        raise ValueError(f"shape mismatch: C {tuple(C.shape)}, A {tuple(A.shape)}, B {tuple(B.shape)}")
+    if A.dtype != C.dtype or B.dtype != C.dtype:
+        raise TypeError("A, B and C must share one element type")
+    for t in (A, B, C):
+        if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+            raise ValueError("operands must be row-major 2-D tensors with unit column stride")
+    fcode = FORMS[form] if isinstance(form, str) else int(form)
+    st = L.pluq_modmm_noalloc(m, n, k, ctypes.c_void_p(C.data_ptr()), _ld(C), ctypes.c_void_p(A.data_ptr()),
+                              _ld(A), ctypes.c_void_p(B.data_ptr()), _ld(B), _dtype_code(C), p, fcode, _stream(C))
+    _check(st, "pluq_modmm_noalloc")
 
 
 def pluq_trsm(side: int, T, B, p: int, form="fp64"):

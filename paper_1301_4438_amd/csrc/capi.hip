@@ -14,6 +14,13 @@
 
 using namespace pluq;
 
+// Scratch of pluq_modmm_noalloc: the INT8 form's digit planes, in a static
+// device array (each device holds its own copy for the life of the
+// process).  Host code uses only the device address from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) int8_t scratch[NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr uint64_t P_MAX = 1ull << 26;
@@ -185,6 +192,88 @@ pluq_status form_check(int form, uint64_t p) {
     if (form == PLUQ_FORM_INT8) return i8_limbs((double)p) > 0 ? PLUQ_OK : PLUQ_ERR_UNSUPPORTED;
     if (form == PLUQ_FORM_FP32) return fp32_kchunk(p) >= 16 ? PLUQ_OK : PLUQ_ERR_UNSUPPORTED;
     return PLUQ_ERR_ARG;
+}
+
+
+// ---------------------------------------------------- MM building block --
+
+pluq_status modmm_check(int64_t m, int64_t n, int64_t k, const void *dC, int64_t ldc, const void *dA, int64_t lda,
+                        const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form) {
+    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return PLUQ_ERR_ARG;
+    if (esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
+    pluq_status s = form_check(form, p);
+    if (s != PLUQ_OK) return s;
+    if (m == 0 || n == 0) return PLUQ_OK;
+    if (!dC || (k > 0 && (!dA || !dB))) return PLUQ_ERR_ARG;
+    if (ldc < n || (k > 0 && (lda < k || ldb < n))) return PLUQ_ERR_ARG;
+    return PLUQ_OK;
+}
+
+// C <- C - A B on the caller's stream; `limb` / `limb_bytes` hold the INT8
+// form's digit planes.  noprof: no event timing (nothing is allocated).
+pluq_status modmm_run(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
+                      const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form, char *limb,
+                      size_t limb_bytes, bool noprof, void *stream) {
+    MMProblem pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.C = dC;
+    pb.ldc = ldc;
+    pb.M = (int32_t)m;
+    pb.N = (int32_t)n;
+    pb.A[0] = dA;
+    pb.lda[0] = lda;
+    pb.B[0] = dB;
+    pb.ldb[0] = ldb;
+    pb.K[0] = (int32_t)k;
+    try {
+        Ctx c;
+        c.dt = (int)dt;
+        c.esz = esize(dt);
+        c.p = p;
+        c.form = form;
+        c.kchunk = (int)fp64_kchunk(p);
+        c.kchunk32 = (int)fp32_kchunk(p);
+        c.st = (hipStream_t)stream;
+        c.noprof = noprof;
+        if (form == PLUQ_FORM_INT8) {
+            // the kernel-level entry always takes the int8 path
+            c.limb = limb;
+            c.limb_bytes = limb_bytes;
+            if (!c.mm_i8(pb)) return PLUQ_ERR_WORKSPACE;
+        } else {
+            c.mm(&pb, 1);
+        }
+    } catch (const DeviceError &e) {
+        set_err("pluq_modmm: HIP call", e.e);
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
+}
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+pluq_status scratch_address(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_err("pluq_modmm_noalloc: hipGetDevice", e);
+        return PLUQ_ERR_DEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_err("pluq_modmm_noalloc: hipGetSymbolAddress", e);
+            return PLUQ_ERR_DEVICE;
+        }
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PLUQ_OK;
 }
 
 }  // namespace
@@ -493,50 +582,32 @@ size_t pluq_modmm_workspace_size(int64_t m, int64_t n, int64_t k, int32_t form) 
 pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
                        const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form, void *dWork,
                        size_t work_bytes, void *stream) {
-    if (m < 0 || n < 0 || k < 0 || m > INT32_MAX || n > INT32_MAX || k > INT32_MAX) return PLUQ_ERR_ARG;
-    if (esize(dt) == 0) return PLUQ_ERR_ARG;
-    if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
-    pluq_status s = form_check(form, p);
-    if (s != PLUQ_OK) return s;
-    if (m == 0 || n == 0) return PLUQ_OK;
-    if (!dC || (k > 0 && (!dA || !dB))) return PLUQ_ERR_ARG;
-    if (ldc < n || (k > 0 && (lda < k || ldb < n))) return PLUQ_ERR_ARG;
-    if (k == 0) return PLUQ_OK;
+    pluq_status s = modmm_check(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form);
+    if (s != PLUQ_OK || m == 0 || n == 0 || k == 0) return s;
     const size_t need = pluq_modmm_workspace_size(m, n, k, form);
     if (need && (!dWork || work_bytes < need)) return PLUQ_ERR_WORKSPACE;
     if (need && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
-    MMProblem pb;
-    std::memset(&pb, 0, sizeof(pb));
-    pb.C = dC;
-    pb.ldc = ldc;
-    pb.M = (int32_t)m;
-    pb.N = (int32_t)n;
-    pb.A[0] = dA;
-    pb.lda[0] = lda;
-    pb.B[0] = dB;
-    pb.ldb[0] = ldb;
-    pb.K[0] = (int32_t)k;
-    try {
-        Ctx c;
-        c.dt = (int)dt;
-        c.esz = esize(dt);
-        c.p = p;
-        c.form = form;
-        c.kchunk = (int)fp64_kchunk(p);
-        c.kchunk32 = (int)fp32_kchunk(p);
-        c.st = (hipStream_t)stream;
-        if (form == PLUQ_FORM_INT8) {
-            // the kernel-level entry always takes the int8 path
-            c.limb = (char *)dWork;
-            c.limb_bytes = work_bytes;
-            if (!c.mm_i8(pb)) return PLUQ_ERR_WORKSPACE;
-        } else {
-            c.mm(&pb, 1);
-        }
-    } catch (const DeviceError &) {
-        return PLUQ_ERR_DEVICE;
+    return modmm_run(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form, (char *)dWork, work_bytes, false, stream);
+}
+
+pluq_status pluq_modmm_noalloc(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
+                               const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form,
+                               void *stream) {
+    pluq_status s = modmm_check(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form);
+    if (s != PLUQ_OK || m == 0 || n == 0 || k == 0) return s;
+    if (form != PLUQ_FORM_INT8)
+        return modmm_run(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form, nullptr, 0, true, stream);
+    // the digit planes of one 64-deep piece must fit in the static scratch
+    const size_t nl = (size_t)i8_limbs((double)p);
+    if (nl * (size_t)(m + n) * 64 > NOALLOC_SCRATCH_BYTES) {
+        std::snprintf(g_err, sizeof(g_err),
+                      "pluq_modmm_noalloc: m + n = %lld above %lld, the most its static scratch serves",
+                      (long long)(m + n), (long long)(NOALLOC_SCRATCH_BYTES / (nl * 64)));
+        return PLUQ_ERR_WORKSPACE;
     }
-    return PLUQ_OK;
+    char *ptr = nullptr;
+    if ((s = scratch_address(&ptr)) != PLUQ_OK) return s;
+    return modmm_run(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form, ptr, NOALLOC_SCRATCH_BYTES, true, stream);
 }
 
 size_t pluq_trsm_workspace_size(int64_t r, pluq_dtype dt) {

@@ -215,29 +215,46 @@ void Ctx::mm(MMProblem *probs, int n) {
 bool Ctx::mm_i8(const MMProblem &pb) {
     const int nl = i8_limbs((double)p);
     const int64_t M = pb.M, N = pb.N;
-    int64_t ks = (int64_t)(limb_bytes / ((size_t)nl * (size_t)(M + N))) / 64 * 64;
+    int64_t ks = (nl > 0) ? (int64_t)(limb_bytes / ((size_t)nl * (size_t)(M + N))) / 64 * 64 : 0;
     ks = std::min<int64_t>(ks, KMAX_I8);
     if (nl == 0 || ks < 64) return false;
+    // Pieces of at most ks positions, operand pair 0 then pair 1, taken in
+    // order (no list is built: the next piece is formed on demand).
     struct Seg { int pair; int64_t k0, len; };
-    std::vector<Seg> segs;
-    for (int s = 0; s < 2; ++s)
-        for (int64_t k0 = 0; k0 < pb.K[s]; k0 += ks) segs.push_back({s, k0, std::min<int64_t>(ks, pb.K[s] - k0)});
+    int cur_pair = 0;
+    int64_t cur_k = 0;
+    auto next = [&](Seg &sg) -> bool {
+        while (cur_pair < 2 && cur_k >= (int64_t)pb.K[cur_pair]) {
+            ++cur_pair;
+            cur_k = 0;
+        }
+        if (cur_pair >= 2) return false;
+        sg.pair = cur_pair;
+        sg.k0 = cur_k;
+        sg.len = std::min<int64_t>(ks, (int64_t)pb.K[cur_pair] - cur_k);
+        cur_k += sg.len;
+        return true;
+    };
     int8_t *a0 = (int8_t *)limb;
-    size_t i = 0;
-    while (i < segs.size()) {
-        // pack consecutive pieces while their padded widths fit in ks
-        size_t j = i;
+    Seg pend;
+    bool have = next(pend);
+    while (have) {
+        // up to two consecutive pieces share a launch while their padded
+        // widths fit in ks
+        Seg grp[2];
+        int ng = 0;
         int64_t kp = 0;
-        while (j < segs.size() && j - i < 2 && kp + (segs[j].len + 63) / 64 * 64 <= ks) {
-            kp += (segs[j].len + 63) / 64 * 64;
-            ++j;
+        while (have && ng < 2 && kp + (pend.len + 63) / 64 * 64 <= ks) {
+            kp += (pend.len + 63) / 64 * 64;
+            grp[ng++] = pend;
+            have = next(pend);
         }
         int8_t *a1 = a0 + M * kp, *b0 = a0 + (size_t)nl * M * kp, *b1 = b0 + N * kp;
         SplitJob jobs[SPLIT_MAX_JOBS];
         int nj = 0;
-        int64_t koff = 0;
-        for (size_t q = i; q < j; ++q) {
-            const Seg &sg = segs[q];
+        int64_t koff = 0, klen = 0;
+        for (int q = 0; q < ng; ++q) {
+            const Seg &sg = grp[q];
             const int64_t w = (sg.len + 63) / 64 * 64;
             SplitJob ja;
             ja.src = (const char *)pb.A[sg.pair] + sg.k0 * (int64_t)esz;
@@ -262,12 +279,11 @@ bool Ctx::mm_i8(const MMProblem &pb) {
             jb.ldd = kp;
             jobs[nj++] = jb;
             koff += w;
+            klen += sg.len;
         }
         const double split_bytes = (double)(M + N) * (double)kp * ((double)esz + nl);
         launch(K_LIMB, 0, split_bytes, [&] { return launch_limb_split(dt, jobs, nj, (double)p, st); });
-        int64_t klen = 0;
-        for (size_t q = i; q < j; ++q) klen += segs[q].len;
-        const bool last = (j == segs.size());
+        const bool last = !have;   // only the last piece reports non-zero outputs
         const int8_t *pa[2] = {a0, a1}, *pbp[2] = {b0, b1};
         const double flops = 2.0 * (double)M * (double)N * (double)klen;
         const double bytes = 2.0 * M * N * (double)esz + (double)(M + N) * (double)kp * nl;
@@ -275,7 +291,6 @@ bool Ctx::mm_i8(const MMProblem &pb) {
             return launch_modmm_i8(dt, pb.C, pb.ldc, (int)M, (int)N, (int)kp, pa, pbp, kp, kp, (double)p,
                                    last ? pb.nzflag : nullptr, pb.nzgen, st);
         });
-        i = j;
     }
     return true;
 }

@@ -105,13 +105,15 @@ struct Ctx {
     // out in the identity order (inputs far from generic stay so; a single
     // failure, as with a small p where tiles fail at random, does not switch).
     int opt_fails = 0;
+    // No per-launch event timing (the entry point that allocates nothing).
+    bool noprof = false;
 
     void check(hipError_t e);
     // Issue one kernel launch (f returns its hipError_t), timed when the
     // profiler is on.
     template <class F> void launch(int cls, double flops, double bytes, F f) {
         size_t idx = 0;
-        const bool timed = (g_prof.mask >> cls) & 1;
+        const bool timed = !noprof && ((g_prof.mask >> cls) & 1);
         if (timed) check(g_prof.begin(st, &idx));
         check(f());
         if (timed) check(g_prof.end(st, idx, cls, flops, bytes));
