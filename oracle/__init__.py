@@ -181,3 +181,66 @@ def leading_rank_profiles(P, Q, r: int, k: int, t: int):
     Q = np.asarray(Q)
     sel = (P[:r] < k) & (Q[:r] < t)
     return np.sort(P[:r][sel]), np.sort(Q[:r][sel])
+
+
+# ---- outputs derived from the PLUQ decomposition by permutation only ------
+#
+# The permutation matrices of the decomposition A = P [L; M] [U V] Q: with
+# the index vectors P, Q (A[P[i], Q[j]] = (L U)[i, j]) they are
+# Pm[P[i], i] = 1 and Qm[j, Q[j]] = 1, so that A = Pm (L U) Qm.
+
+def _perm_matrices(P, Q):
+    m, n = len(P), len(Q)
+    Pm = np.zeros((m, m), np.int64)
+    Pm[np.asarray(P, np.int64), np.arange(m)] = 1
+    Qm = np.zeros((n, n), np.int64)
+    Qm[np.arange(n), np.asarray(Q, np.int64)] = 1
+    return Pm, Qm
+
+
+def leu(P, Q, r: int, X):
+    """The LEU decomposition of Section 3 from (P, Q, r, X = [L\\U V; M 0]):
+        Lbar = Pm [L 0; M I] Pm^T,  E = Pm [I_r 0; 0 0] Qm,  Ubar = Qm^T [U V; 0 I] Qm,
+    written out with the permutation matrices.  Returns (Lbar, E, Ubar),
+    int64 (E is 0/1); A = Lbar E Ubar mod p."""
+    X = np.asarray(X, np.int64)
+    m, n = X.shape
+    Pm, Qm = _perm_matrices(P, Q)
+    Lb = np.eye(m, dtype=np.int64)
+    Lb[:, :r] = np.tril(X[:, :r], -1)
+    Lb[np.arange(r), np.arange(r)] = 1
+    Ub = np.eye(n, dtype=np.int64)
+    Ub[:r, :] = np.triu(X[:r, :])
+    I_r = np.zeros((m, n), np.int64)
+    I_r[np.arange(r), np.arange(r)] = 1
+    return Pm @ Lb @ Pm.T, Pm @ I_r @ Qm, Qm.T @ Ub @ Qm
+
+
+def column_echelon(P, Q, r: int, X):
+    """(C, R, rows): the columns of Lbar at the pivot rows taken in ascending
+    order (the row rank profile, `rows`) and the rows of Ubar at their paired
+    columns, so that A = C R with C (m x r) in column echelon form."""
+    Lb, E, Ub = leu(P, Q, r, X)
+    rows = np.sort(np.asarray(P[:r], np.int64))
+    cols = np.array([int(np.nonzero(E[i])[0][0]) for i in rows], np.int64) if r else np.zeros(0, np.int64)
+    return Lb[:, rows], Ub[cols, :], rows
+
+
+def row_echelon(P, Q, r: int, X):
+    """(E_row, L_E, cols): the rows of Ubar at the pivot columns taken in
+    ascending order (the column rank profile, `cols`) and the columns of Lbar
+    at their paired rows, so that A = L_E E_row with E_row (r x n) in row
+    echelon form."""
+    Lb, E, Ub = leu(P, Q, r, X)
+    cols = np.sort(np.asarray(Q[:r], np.int64))
+    rows = np.array([int(np.nonzero(E[:, j])[0][0]) for j in cols], np.int64) if r else np.zeros(0, np.int64)
+    return Ub[cols, :], Lb[:, rows], cols
+
+
+def leading_rank(P, Q, r: int, k: int, t: int) -> int:
+    """Rank of the leading k x t sub-matrix: the number of non-zero entries of
+    the rank profile matrix in it (Section 4, corollary of the rank profile
+    matrix lemma)."""
+    P = np.asarray(P)
+    Q = np.asarray(Q)
+    return int(np.sum((P[:r] < k) & (Q[:r] < t)))
