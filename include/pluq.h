@@ -211,6 +211,80 @@ pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n,
                               int64_t *d_r, const pluq_opts *opts, void *dWork,
                               size_t work_bytes, void *stream);
 
+/* ---- outputs read off a decomposition by permutation (Sections 3, 4) ----
+ *
+ * All take the result of pluq_modp -- the packed X = [L\U V; M 0] (m x n,
+ * row-major, ldx) and the device index vectors P, Q with the rank r -- and
+ * a device workspace of pluq_post_workspace_size(m, n) bytes (256-byte
+ * aligned); they are asynchronous on `stream` and leave X, P and Q
+ * unchanged.  P and Q must be the vectors pluq_modp returned (entries out of
+ * range are skipped, never used to address memory, but then the outputs are
+ * unspecified).
+ */
+size_t pluq_post_workspace_size(int64_t m, int64_t n);
+
+/*
+ * The LEU decomposition of Section 3, A = Lbar E Ubar:
+ *   Lbar = P [L 0; M I] P^T   (m x m, unit lower triangular by Section 3's
+ *                              theorem) into dLbar (ldl >= m);
+ *   Ubar = Q^T [U V; 0 I] Q   (n x n, upper triangular with non-zero
+ *                              diagonal) into dUbar (ldu >= n);
+ *   E = P [I_r 0; 0 0] Q      the rank profile matrix, as dErow (length m,
+ *                              int64, may be NULL): the column of row i's
+ *                              non-zero entry, or -1.
+ * Element type dt for X, Lbar and Ubar.
+ */
+pluq_status pluq_leu(int64_t m, int64_t n, int64_t r, const void *dX, int64_t ldx,
+                     pluq_dtype dt, const int64_t *dP, const int64_t *dQ, void *dLbar,
+                     int64_t ldl, void *dUbar, int64_t ldu, int64_t *dErow, void *dWork,
+                     size_t work_bytes, void *stream);
+
+/*
+ * Echelon factorizations taken from the LEU factors by permutation only:
+ *   PLUQ_ECHELON_COLUMN: A = C R with C = the columns of Lbar at the pivot
+ *     rows in ascending order (m x r, column echelon form: column k is zero
+ *     above row prof[k], 1 there) into dF (ldf >= r), R = the rows of Ubar at
+ *     the paired columns (r x n) into dG (ldg >= n), and prof = the row rank
+ *     profile (r int64) -- the echelon factor of a CUP decomposition;
+ *   PLUQ_ECHELON_ROW: A = L_E E with E = the rows of Ubar at the pivot
+ *     columns in ascending order (r x n, row echelon form: row k is zero
+ *     left of column prof[k], non-zero there) into dF (ldf >= n), L_E = the
+ *     columns of Lbar at the paired rows (m x r) into dG (ldg >= r), and
+ *     prof = the column rank profile -- the echelon factor of a PLE
+ *     decomposition.
+ * (The co-factors R and L_E are not triangular in general: the pivots of
+ * Algorithm 1 come in the order of its recursion, not in the row or column
+ * order a CUP or PLE elimination would take.)
+ */
+enum { PLUQ_ECHELON_COLUMN = 0, PLUQ_ECHELON_ROW = 1 };
+pluq_status pluq_echelon(int32_t kind, int64_t m, int64_t n, int64_t r, const void *dX,
+                         int64_t ldx, pluq_dtype dt, const int64_t *dP, const int64_t *dQ,
+                         void *dF, int64_t ldf, void *dG, int64_t ldg, int64_t *dProf,
+                         void *dWork, size_t work_bytes, void *stream);
+
+/*
+ * Ranks of leading sub-matrices, a batch of queries on the device (Section
+ * 4: the rank of the leading k x t block is the number of rank profile
+ * matrix entries in it): dranks[q] = rank(A[0:dk[q], 0:dt[q]]) for
+ * q < nq (device int64 arrays).
+ */
+pluq_status pluq_leading_ranks(int64_t m, int64_t n, int64_t r, const int64_t *dP,
+                               const int64_t *dQ, int64_t nq, const int64_t *dk,
+                               const int64_t *dt, int64_t *dranks, void *dWork,
+                               size_t work_bytes, void *stream);
+
+/*
+ * Row and column rank profiles of the leading k x t sub-matrix on the
+ * device (the device form of pluq_leading_rank_profiles): drows, dcols
+ * (device, capacity >= r) receive the sorted profiles and dcount[0],
+ * dcount[1] (device int64) their lengths (equal: the block's rank).
+ */
+pluq_status pluq_leading_rank_profiles_device(int64_t m, int64_t n, int64_t r,
+                                              const int64_t *dP, const int64_t *dQ,
+                                              int64_t k, int64_t t, int64_t *drows,
+                                              int64_t *dcols, int64_t *dcount, void *dWork,
+                                              size_t work_bytes, void *stream);
+
 /* ---- building blocks of Section 2 (device, for direct use and tests) ---- */
 
 /*

@@ -97,6 +97,19 @@ def load():
     L.pluq_modmm.restype = ctypes.c_int
     L.pluq_modmm.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                              ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    L.pluq_post_workspace_size.restype = ctypes.c_size_t
+    L.pluq_post_workspace_size.argtypes = [_i64, _i64]
+    L.pluq_leu.restype = ctypes.c_int
+    L.pluq_leu.argtypes = [_i64, _i64, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _vp,
+                           ctypes.c_size_t, _vp]
+    L.pluq_echelon.restype = ctypes.c_int
+    L.pluq_echelon.argtypes = [ctypes.c_int32, _i64, _i64, _i64, _vp, _i64, ctypes.c_int, _vp, _vp, _vp, _i64, _vp,
+                               _i64, _vp, _vp, ctypes.c_size_t, _vp]
+    L.pluq_leading_ranks.restype = ctypes.c_int
+    L.pluq_leading_ranks.argtypes = [_i64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.pluq_leading_rank_profiles_device.restype = ctypes.c_int
+    L.pluq_leading_rank_profiles_device.argtypes = [_i64, _i64, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp,
+                                                    ctypes.c_size_t, _vp]
     L.pluq_modmm_noalloc.restype = ctypes.c_int
     L.pluq_modmm_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                                      ctypes.c_int32, _vp]
@@ -334,6 +347,78 @@ def pluq_modmm(C, A, B, p: int, form="fp64", work=None):
                       ctypes.c_void_p(work.data_ptr() if work is not None else 0),
                       work.numel() if work is not None else 0, _stream(C))
     _check(st, "pluq_modmm")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def _post_ws(m, n, device):
+    return _workspace(device, int(load().pluq_post_workspace_size(m, n)))
+
+
+def pluq_leu(X, P, Q, r: int):
+    """LEU decomposition (Section 3) of a finished decomposition (X packed,
+    P, Q device int64): returns (Lbar m x m, Ubar n x n, Erow) with Erow[i]
+    the column of row i's rank-profile entry or -1.  Asynchronous."""
+    import torch
+    L = load()
+    m, n = X.shape
+    Lb = torch.empty((m, m), dtype=X.dtype, device=X.device)
+    Ub = torch.empty((n, n), dtype=X.dtype, device=X.device)
+    Er = torch.empty(m, dtype=torch.int64, device=X.device)
+    ws = _post_ws(m, n, X.device)
+    st = L.pluq_leu(m, n, int(r), _ptr(X), _ld(X) if m else max(n, 1), _dtype_code(X), _ptr(P), _ptr(Q), _ptr(Lb),
+                    max(m, 1), _ptr(Ub), max(n, 1), _ptr(Er), _ptr(ws), ws.numel(), _stream(X))
+    _check(st, "pluq_leu")
+    return Lb, Ub, Er
+
+
+def pluq_echelon(X, P, Q, r: int, kind="column"):
+    """kind "column": (C m x r, R r x n, row rank profile), A = C R;
+    kind "row": (E r x n, L_E m x r, column rank profile), A = L_E E."""
+    import torch
+    L = load()
+    m, n = X.shape
+    k = 0 if kind == "column" else 1
+    F = torch.empty((m, r) if k == 0 else (r, n), dtype=X.dtype, device=X.device)
+    G = torch.empty((r, n) if k == 0 else (m, r), dtype=X.dtype, device=X.device)
+    prof = torch.empty(r, dtype=torch.int64, device=X.device)
+    ws = _post_ws(m, n, X.device)
+    st = L.pluq_echelon(k, m, n, int(r), _ptr(X), _ld(X) if m else max(n, 1), _dtype_code(X), _ptr(P), _ptr(Q),
+                        _ptr(F), max(F.shape[1], 1), _ptr(G), max(G.shape[1], 1), _ptr(prof), _ptr(ws),
+                        ws.numel(), _stream(X))
+    _check(st, "pluq_echelon")
+    return F, G, prof
+
+
+def pluq_leading_ranks(P, Q, r: int, ks, ts):
+    """Ranks of the leading ks[q] x ts[q] blocks (device int64 tensors)."""
+    import torch
+    L = load()
+    m, n = P.numel(), Q.numel()
+    out = torch.empty(ks.numel(), dtype=torch.int64, device=ks.device)
+    ws = _post_ws(m, n, ks.device)
+    st = L.pluq_leading_ranks(m, n, int(r), _ptr(P), _ptr(Q), ks.numel(), _ptr(ks), _ptr(ts), _ptr(out), _ptr(ws),
+                              ws.numel(), _stream(ks))
+    _check(st, "pluq_leading_ranks")
+    return out
+
+
+def pluq_leading_rank_profiles_device(P, Q, r: int, k: int, t: int):
+    """(rows, cols) of the leading k x t block, sorted, as device tensors."""
+    import torch
+    L = load()
+    m, n = P.numel(), Q.numel()
+    rows = torch.empty(max(r, 1), dtype=torch.int64, device=P.device)
+    cols = torch.empty(max(r, 1), dtype=torch.int64, device=P.device)
+    cnt = torch.zeros(2, dtype=torch.int64, device=P.device)
+    ws = _post_ws(m, n, P.device)
+    st = L.pluq_leading_rank_profiles_device(m, n, int(r), _ptr(P), _ptr(Q), int(k), int(t), _ptr(rows),
+                                             _ptr(cols), _ptr(cnt), _ptr(ws), ws.numel(), _stream(P))
+    _check(st, "pluq_leading_rank_profiles_device")
+    c = cnt.cpu().tolist()
+    return rows[:c[0]], cols[:c[1]]
 
 
 def pluq_modmm_noalloc(C, A, B, p: int, form="fp64"):

@@ -679,3 +679,174 @@ void pluq_last_stats(int64_t *nodes, int64_t *basecases, int64_t *launches, int6
 }
 
 }  // extern "C"
+
+// ------------------------------------------- outputs derived by permutation --
+
+size_t pluq_post_workspace_size(int64_t m, int64_t n) {
+    if (m < 0 || n < 0) return 0;
+    const size_t mm = (size_t)std::max<int64_t>(m, 1), nn = (size_t)std::max<int64_t>(n, 1);
+    // inverse maps, pairings, a sorted profile and two composed maps (int32)
+    return align_up(4 * mm) * 2 + align_up(4 * nn) * 2 + align_up(4 * std::max(mm, nn)) * 3;
+}
+
+namespace {
+
+struct PostWs {
+    int32_t *pinv, *qinv, *rowpair, *colpair, *sel, *map1, *map2;
+};
+
+PostWs post_layout(int64_t m, int64_t n, void *dWork) {
+    const size_t mm = (size_t)std::max<int64_t>(m, 1), nn = (size_t)std::max<int64_t>(n, 1);
+    const size_t mx = std::max(mm, nn);
+    char *w = (char *)dWork;
+    PostWs ws;
+    ws.pinv = (int32_t *)w;
+    w += align_up(4 * mm);
+    ws.rowpair = (int32_t *)w;
+    w += align_up(4 * mm);
+    ws.qinv = (int32_t *)w;
+    w += align_up(4 * nn);
+    ws.colpair = (int32_t *)w;
+    w += align_up(4 * nn);
+    ws.sel = (int32_t *)w;
+    w += align_up(4 * mx);
+    ws.map1 = (int32_t *)w;
+    w += align_up(4 * mx);
+    ws.map2 = (int32_t *)w;
+    return ws;
+}
+
+pluq_status post_check(int64_t m, int64_t n, int64_t r, const int64_t *dP, const int64_t *dQ, void *dWork,
+                       size_t work_bytes) {
+    if (m < 0 || n < 0 || r < 0 || r > std::min(m, n) || m > INT32_MAX || n > INT32_MAX) return PLUQ_ERR_ARG;
+    if ((m > 0 && !dP) || (n > 0 && !dQ)) return PLUQ_ERR_ARG;
+    if (!dWork || work_bytes < pluq_post_workspace_size(m, n)) return PLUQ_ERR_WORKSPACE;
+    if ((uintptr_t)dWork % ALIGN) return PLUQ_ERR_ARG;
+    return PLUQ_OK;
+}
+
+// Inverse permutations and the rank profile matrix's row <-> column pairing.
+void post_maps(int64_t m, int64_t n, int64_t r, const int64_t *dP, const int64_t *dQ, const PostWs &ws,
+               hipStream_t st) {
+    auto ck = [](hipError_t e) { if (e != hipSuccess) throw DeviceError{e}; };
+    ck(launch_fill_i32(ws.pinv, m, 0, st));
+    ck(launch_fill_i32(ws.qinv, n, 0, st));
+    ck(launch_fill_i32(ws.rowpair, m, -1, st));
+    ck(launch_fill_i32(ws.colpair, n, -1, st));
+    ck(launch_inverse_map(dP, m, ws.pinv, st));
+    ck(launch_inverse_map(dQ, n, ws.qinv, st));
+    ck(launch_pair(dP, dQ, m, n, r, ws.rowpair, ws.colpair, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+pluq_status pluq_leu(int64_t m, int64_t n, int64_t r, const void *dX, int64_t ldx, pluq_dtype dt, const int64_t *dP,
+                     const int64_t *dQ, void *dLbar, int64_t ldl, void *dUbar, int64_t ldu, int64_t *dErow,
+                     void *dWork, size_t work_bytes, void *stream) {
+    pluq_status s = post_check(m, n, r, dP, dQ, dWork, work_bytes);
+    if (s != PLUQ_OK) return s;
+    if (esize(dt) == 0) return PLUQ_ERR_ARG;
+    if ((m > 0 && n > 0 && (!dX || ldx < n)) || (m > 0 && (!dLbar || ldl < m)) || (n > 0 && (!dUbar || ldu < n)))
+        return PLUQ_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const PostWs ws = post_layout(m, n, dWork);
+    try {
+        post_maps(m, n, r, dP, dQ, ws, st);
+        auto ck = [](hipError_t e) { if (e != hipSuccess) throw DeviceError{e}; };
+        ck(launch_post_gather((int)dt, false, dX, ldx, r, dLbar, ldl, m, m, ws.pinv, ws.pinv, st));
+        ck(launch_post_gather((int)dt, true, dX, ldx, r, dUbar, ldu, n, n, ws.qinv, ws.qinv, st));
+        if (dErow) ck(launch_widen(ws.rowpair, m, dErow, st));
+    } catch (const DeviceError &e) {
+        set_err("pluq_leu: HIP call", e.e);
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
+}
+
+pluq_status pluq_echelon(int32_t kind, int64_t m, int64_t n, int64_t r, const void *dX, int64_t ldx, pluq_dtype dt,
+                         const int64_t *dP, const int64_t *dQ, void *dF, int64_t ldf, void *dG, int64_t ldg,
+                         int64_t *dProf, void *dWork, size_t work_bytes, void *stream) {
+    pluq_status s = post_check(m, n, r, dP, dQ, dWork, work_bytes);
+    if (s != PLUQ_OK) return s;
+    if ((kind != PLUQ_ECHELON_COLUMN && kind != PLUQ_ECHELON_ROW) || esize(dt) == 0) return PLUQ_ERR_ARG;
+    if (m > 0 && n > 0 && (!dX || ldx < n)) return PLUQ_ERR_ARG;
+    if (r > 0) {
+        // F: m x r (column echelon) or r x n (row echelon); G the other factor
+        const int64_t fcols = kind == PLUQ_ECHELON_COLUMN ? r : n, gcols = kind == PLUQ_ECHELON_COLUMN ? n : r;
+        if (!dF || !dG || ldf < fcols || ldg < gcols) return PLUQ_ERR_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const PostWs ws = post_layout(m, n, dWork);
+    try {
+        post_maps(m, n, r, dP, dQ, ws, st);
+        if (r == 0) return PLUQ_OK;
+        auto ck = [](hipError_t e) { if (e != hipSuccess) throw DeviceError{e}; };
+        ck(launch_fill_i32(ws.sel, std::max(m, n), 0, st));
+        if (kind == PLUQ_ECHELON_COLUMN) {
+            // pivot rows ascending (the row rank profile); C = Lbar[:, rows],
+            // R = Ubar[paired columns, :]
+            ck(launch_compact(ws.rowpair, m, n, r, ws.sel, dProf, nullptr, st));
+            ck(launch_compose(ws.pinv, ws.sel, nullptr, r, ws.map1, st));
+            ck(launch_compose(ws.qinv, ws.sel, ws.rowpair, r, ws.map2, st));
+            ck(launch_post_gather((int)dt, false, dX, ldx, r, dF, ldf, m, r, ws.pinv, ws.map1, st));
+            ck(launch_post_gather((int)dt, true, dX, ldx, r, dG, ldg, r, n, ws.map2, ws.qinv, st));
+        } else {
+            // pivot columns ascending (the column rank profile);
+            // E = Ubar[columns, :], L_E = Lbar[:, paired rows]
+            ck(launch_compact(ws.colpair, n, m, r, ws.sel, dProf, nullptr, st));
+            ck(launch_compose(ws.qinv, ws.sel, nullptr, r, ws.map1, st));
+            ck(launch_compose(ws.pinv, ws.sel, ws.colpair, r, ws.map2, st));
+            ck(launch_post_gather((int)dt, true, dX, ldx, r, dF, ldf, r, n, ws.map1, ws.qinv, st));
+            ck(launch_post_gather((int)dt, false, dX, ldx, r, dG, ldg, m, r, ws.pinv, ws.map2, st));
+        }
+    } catch (const DeviceError &e) {
+        set_err("pluq_echelon: HIP call", e.e);
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
+}
+
+pluq_status pluq_leading_ranks(int64_t m, int64_t n, int64_t r, const int64_t *dP, const int64_t *dQ, int64_t nq,
+                               const int64_t *dk, const int64_t *dt_, int64_t *dranks, void *dWork,
+                               size_t work_bytes, void *stream) {
+    pluq_status s = post_check(m, n, r, dP, dQ, dWork, work_bytes);
+    if (s != PLUQ_OK) return s;
+    if (nq < 0 || (nq > 0 && (!dk || !dt_ || !dranks))) return PLUQ_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const PostWs ws = post_layout(m, n, dWork);
+    try {
+        post_maps(m, n, r, dP, dQ, ws, st);
+        const hipError_t e = launch_leading_ranks(ws.rowpair, m, dk, dt_, nq, dranks, st);
+        if (e != hipSuccess) throw DeviceError{e};
+    } catch (const DeviceError &e) {
+        set_err("pluq_leading_ranks: HIP call", e.e);
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
+}
+
+pluq_status pluq_leading_rank_profiles_device(int64_t m, int64_t n, int64_t r, const int64_t *dP, const int64_t *dQ,
+                                              int64_t k, int64_t t, int64_t *drows, int64_t *dcols,
+                                              int64_t *dcount, void *dWork, size_t work_bytes, void *stream) {
+    pluq_status s = post_check(m, n, r, dP, dQ, dWork, work_bytes);
+    if (s != PLUQ_OK) return s;
+    if (k < 0 || t < 0 || !dcount || (r > 0 && (!drows || !dcols))) return PLUQ_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const PostWs ws = post_layout(m, n, dWork);
+    try {
+        post_maps(m, n, r, dP, dQ, ws, st);
+        auto ck = [](hipError_t e) { if (e != hipSuccess) throw DeviceError{e}; };
+        // rows i < k whose pivot column is < t, and columns j < t whose pivot
+        // row is < k, both ascending
+        ck(launch_compact(ws.rowpair, std::min(k, m), t, r, nullptr, drows, dcount, st));
+        ck(launch_compact(ws.colpair, std::min(t, n), k, r, nullptr, dcols, dcount + 1, st));
+    } catch (const DeviceError &e) {
+        set_err("pluq_leading_rank_profiles_device: HIP call", e.e);
+        return PLUQ_ERR_DEVICE;
+    }
+    return PLUQ_OK;
+}
+
+}  // extern "C"

@@ -149,6 +149,22 @@ hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, do
 int bc_capacity();        // maximum rows (and columns) of a base-case tile
 hipError_t bc_init();     // one-time set-up of the base-case kernels
 
+// ---- outputs derived by permutation (k_post.hip) ----
+hipError_t launch_fill_i32(int32_t *x, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_inverse_map(const int64_t *P, int64_t n, int32_t *inv, hipStream_t st);
+hipError_t launch_pair(const int64_t *P, const int64_t *Q, int64_t m, int64_t n, int64_t r, int32_t *rowpair,
+                       int32_t *colpair, hipStream_t st);
+hipError_t launch_compact(const int32_t *pair, int64_t lim, int64_t plim, int64_t cap, int32_t *out, int64_t *out64,
+                          int64_t *count, hipStream_t st);
+hipError_t launch_compose(const int32_t *inv, const int32_t *sel, const int32_t *pair, int64_t n, int32_t *out,
+                          hipStream_t st);
+hipError_t launch_post_gather(int dtype, bool upper, const void *X, int64_t ldx, int64_t r, void *out, int64_t ldo,
+                              int64_t rows, int64_t cols, const int32_t *rowmap, const int32_t *colmap,
+                              hipStream_t st);
+hipError_t launch_widen(const int32_t *in, int64_t n, int64_t *out, hipStream_t st);
+hipError_t launch_leading_ranks(const int32_t *rowpair, int64_t m, const int64_t *ks, const int64_t *ts, int64_t nq,
+                                int64_t *rank, hipStream_t st);
+
 }  // namespace pluq
 
 #include <hip/hip_ext.h>
