@@ -97,6 +97,12 @@ typedef struct {
                                    (0: 4 for panel 8, 2 for panel 16; tuning only) */
     int32_t no_speculation;     /* non-zero: no speculative first attempt (pluq_modp) and
                                    no room for it in pluq_workspace_size */
+    int32_t branches;           /* concurrent recursion branches of pluq_modp: the calls
+                                   PLUQ(F) and PLUQ(G) of a node, both at least 256 x 256,
+                                   run side by side while a branch is free (0: 4; 1: none;
+                                   at most 16); each branch needs its own workspace share
+                                   (pluq_workspace_size counts them); the result does not
+                                   depend on it */
 } pluq_opts;
 
 /* Human-readable name of a status code (static storage). */

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "driver.hpp"
@@ -136,7 +137,10 @@ int bc_cap() {
 }
 
 struct Layout {
-    size_t stat_off, idx_off, tab_off, w_off, w2_off, scratch_off, limb_off, spec_off, total;
+    // branch 0 (the caller's) at offset 0; branch b at b * branch_bytes
+    size_t stat_off, idx_off, w_off, w2_off, scratch_off, limb_off, branch_bytes;
+    int nbranch;
+    size_t tab_off, spec_off, total;
     size_t idx_elems, scratch_bytes, tab_bytes, w_bytes, limb_bytes, spec_bytes;
 };
 
@@ -144,32 +148,99 @@ struct Layout {
 // before a speculative decomposition so that a failed one can start again.
 constexpr size_t SPEC_MAX_BYTES = (size_t)1 << 30;
 
+// Concurrent recursion branches (PLUQ(F) || PLUQ(G)) by default, and the
+// smallest F and G (in each dimension) that are run side by side.
+constexpr int DEFAULT_BRANCHES = 4;
+constexpr int64_t FORK_MIN_DIM = 256;
+
 // Diagonal-block inverses of a triangle of order r (TRSM).
 size_t trsm_w_bytes(int64_t r, size_t esz) {
     return (size_t)((r + TRSM_NB - 1) / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
 }
 
-Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec) {
+int branches_for(int64_t m, int64_t n, const pluq_opts *o) {
+    if (std::min(m, n) < 2 * FORK_MIN_DIM) return 1;
+    const int b = (o && o->branches > 0) ? o->branches : DEFAULT_BRANCHES;
+    return std::min(b, 16);
+}
+
+Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec, int nbranch) {
     Layout L;
     L.idx_elems = (size_t)(4 * (m + n) + 65536);
     const size_t full = (size_t)m * (size_t)n * esz;
     const size_t strip = (size_t)64 * (size_t)std::max<int64_t>(std::max<int64_t>(m, n), 1) * esz;
     L.scratch_bytes = std::max(std::min(full, (size_t)256 << 20), std::min(full, strip));
     if (L.scratch_bytes == 0) L.scratch_bytes = ALIGN;
+    L.w_bytes = trsm_w_bytes(std::min(m, n), esz);
+    L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0) ? limb_bytes_for(m, n, p) : 0;
     L.stat_off = 0;
     L.idx_off = align_up(STAT_WORDS * sizeof(int32_t));
-    L.tab_bytes = (p <= 65536) ? BC_TABLE_RESERVE : 0;
-    L.tab_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
-    L.w_bytes = trsm_w_bytes(std::min(m, n), esz);
-    L.w_off = L.tab_off + align_up(L.tab_bytes);
+    L.w_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
     L.w2_off = L.w_off + align_up(L.w_bytes);   // the upper solve of a node's pair
     L.scratch_off = L.w2_off + align_up(L.w_bytes);
-    L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0) ? limb_bytes_for(m, n, p) : 0;
     L.limb_off = L.scratch_off + align_up(L.scratch_bytes);
+    L.branch_bytes = L.limb_off + align_up(L.limb_bytes);
+    L.nbranch = nbranch;
+    L.tab_bytes = (p <= 65536) ? BC_TABLE_RESERVE : 0;
+    L.tab_off = (size_t)nbranch * L.branch_bytes;
     L.spec_bytes = (spec && full <= SPEC_MAX_BYTES) ? full : 0;
-    L.spec_off = L.limb_off + align_up(L.limb_bytes);
+    L.spec_off = L.tab_off + align_up(L.tab_bytes);
     L.total = L.spec_off + align_up(L.spec_bytes);
     return L;
+}
+
+Branch branch_at(char *w, const Layout &L, int b) {
+    char *base = w + (size_t)b * L.branch_bytes;
+    Branch br;
+    br.d_stat = (int32_t *)(base + L.stat_off);
+    br.d_idx = (int32_t *)(base + L.idx_off);
+    br.idx_cap = L.idx_elems;
+    br.trsm_w = base + L.w_off;
+    br.trsm_w2 = base + L.w2_off;
+    br.scratch = base + L.scratch_off;
+    br.scratch_bytes = L.scratch_bytes;
+    if (L.limb_bytes) {
+        br.limb = base + L.limb_off;
+        br.limb_bytes = L.limb_bytes;
+    }
+    return br;
+}
+
+// Streams and events of the helper branches, created once per calling
+// thread and device (default priority) and kept.
+struct HelperCache {
+    int dev = -1;
+    std::vector<hipStream_t> stream;
+    std::vector<hipEvent_t> ev;
+    std::vector<std::unique_ptr<Worker>> worker;
+};
+thread_local HelperCache g_help;
+
+bool helpers_ready(int dev, size_t count) {
+    if (g_help.dev != dev) {
+        g_help = HelperCache();
+        g_help.dev = dev;
+    }
+    while (g_help.stream.size() < count) {
+        hipStream_t s = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            set_err("hipStreamCreateWithFlags (helper branch)", e);
+            return false;
+        }
+        g_help.stream.push_back(s);
+    }
+    while (g_help.worker.size() < count) g_help.worker.push_back(std::unique_ptr<Worker>(new Worker()));
+    while (g_help.ev.size() < 2 * count) {
+        hipEvent_t ev = nullptr;
+        hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            set_err("hipEventCreateWithFlags (helper branch)", e);
+            return false;
+        }
+        g_help.ev.push_back(ev);
+    }
+    return true;
 }
 
 pluq_status check_common(int64_t m, int64_t n, int64_t lda, pluq_dtype dt, uint64_t p, const pluq_opts *o) {
@@ -179,7 +250,7 @@ pluq_status check_common(int64_t m, int64_t n, int64_t lda, pluq_dtype dt, uint6
     if (p < 2 || p >= P_MAX) return PLUQ_ERR_MODULUS;
     if (o) {
         if (o->form != PLUQ_FORM_FP64 && o->form != PLUQ_FORM_INT8 && o->form != PLUQ_FORM_FP32) return PLUQ_ERR_ARG;
-        if (o->cutoff_override < 0) return PLUQ_ERR_ARG;
+        if (o->cutoff_override < 0 || o->branches < 0) return PLUQ_ERR_ARG;
     }
     return PLUQ_OK;
 }
@@ -300,7 +371,8 @@ const char *pluq_last_error(void) { return g_err; }
 
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
-    return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64, !(opts && opts->no_speculation)).total;
+    return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64, !(opts && opts->no_speculation),
+                  branches_for(m, n, opts)).total;
 }
 
 pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
@@ -314,7 +386,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
     const int form = opts ? opts->form : PLUQ_FORM_FP64;
     if ((s = form_check(form, p)) != PLUQ_OK) return s;
     const size_t esz = esize(dt);
-    const Layout L = layout(m, n, esz, p, form, !(opts && opts->no_speculation));
+    const Layout L = layout(m, n, esz, p, form, !(opts && opts->no_speculation), branches_for(m, n, opts));
     if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
     if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
 
@@ -340,18 +412,36 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             c.d_stat = g_pin.stat_dev;
             c.stat_mapped = true;
         }
-        c.d_idx = (int32_t *)(w + L.idx_off);
-        c.idx_cap = L.idx_elems;
-        c.scratch = w + L.scratch_off;
-        c.scratch_bytes = L.scratch_bytes;
-        c.trsm_w = w + L.w_off;
-        c.trsm_w2 = w + L.w2_off;
-        if (L.limb_bytes) {
-            c.limb = w + L.limb_off;
-            c.limb_bytes = L.limb_bytes;
-        }
+        c.use_branch(branch_at(w, L, 0));
         c.h_idx = g_pin.idx;
         c.h_stat = g_pin.stat;
+        // helper branches for PLUQ(F) || PLUQ(G)
+        ForkPool pool;
+        if (L.nbranch > 1 && m > 0 && n > 0) {
+            int dev = 0;
+            c.check(hipGetDevice(&dev));
+            if (!helpers_ready(dev, (size_t)L.nbranch - 1)) return PLUQ_ERR_DEVICE;
+            pool.dev = dev;
+            pool.min_dim = FORK_MIN_DIM;
+            for (int b = 1; b < L.nbranch; ++b) {
+                pool.slot.push_back(branch_at(w, L, b));
+                pool.stream.push_back(g_help.stream[(size_t)b - 1]);
+                pool.ev_start.push_back(g_help.ev[2 * ((size_t)b - 1)]);
+                pool.ev_done.push_back(g_help.ev[2 * ((size_t)b - 1) + 1]);
+                pool.worker.push_back(g_help.worker[(size_t)b - 1].get());
+                pool.busy.push_back(0);
+            }
+            const size_t idx_elems = L.idx_elems;
+            pool.bind_thread = [idx_elems](Ctx &h) {
+                if (!ensure_pinned(idx_elems, 0)) return false;
+                h.h_idx = g_pin.idx;
+                h.h_stat = g_pin.stat;
+                h.stat_mapped = g_pin.stat_dev != nullptr;
+                if (h.stat_mapped) h.d_stat = g_pin.stat_dev;
+                return true;
+            };
+            c.pool = &pool;
+        }
         if (L.tab_bytes && bc_table_bytes((double)p) && m > 0 && n > 0) {
             c.inv_table = (uint16_t *)(w + L.tab_off);
             c.cap = std::min<int64_t>(c.cap, bc_tile_limit((double)p));

@@ -21,7 +21,9 @@
 // not the identity.
 #include <algorithm>
 #include <cstring>
+#include <exception>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "driver.hpp"
@@ -667,8 +669,8 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
     }
 
     std::vector<int32_t> P2, Q2, P3, Q3;
-    const int64_t r2 = node(bF.i, bF.j, bF.m, bF.n, zFGH[0], P2, Q2);   // PLUQ(F)
-    const int64_t r3 = node(bG.i, bG.j, bG.m, bG.n, zFGH[1], P3, Q3);   // PLUQ(G)
+    int64_t r2 = 0, r3 = 0;
+    node_pair(bF, zFGH[0], bG, zFGH[1], r2, r3, P2, Q2, P3, Q3);      // PLUQ(F), PLUQ(G)
 
     perm_rows(gi + r1, gj, k - r1, r1, P2);                    // M1 <- P2^T M1
     perm_rows(gi + k, gj, m - k, r1, P3);                      // E  <- P3^T E
@@ -754,6 +756,159 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
     for (int64_t t = r3; t < h - r1; ++t) pcol.push_back(Q1[r1 + Q3[t]]);
     for (int64_t t = r4; t < n - h - r2; ++t) pcol.push_back((int32_t)(h + Q2[r2 + Q4[t]]));
     return r1 + r2 + r3 + r4;
+}
+
+// ----------------------------------------------------------- branches --
+
+Worker::Worker() {
+    th = std::thread([this] {
+        std::unique_lock<std::mutex> lock(mu);
+        for (;;) {
+            cv.wait(lock, [&] { return quit || static_cast<bool>(job); });
+            if (!job) return;   // asked to quit with nothing pending
+            std::function<void()> j = std::move(job);
+            job = nullptr;
+            lock.unlock();
+            j();
+            lock.lock();
+            busy = false;
+            cv.notify_all();
+        }
+    });
+}
+
+Worker::~Worker() {
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        quit = true;
+    }
+    cv.notify_all();
+    th.join();
+}
+
+void Worker::post(std::function<void()> j) {
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        job = std::move(j);
+        busy = true;
+    }
+    cv.notify_all();
+}
+
+void Worker::wait() {
+    std::unique_lock<std::mutex> lock(mu);
+    cv.wait(lock, [&] { return !busy; });
+}
+
+int ForkPool::acquire() {
+    std::lock_guard<std::mutex> lock(mu);
+    for (size_t s = 0; s < busy.size(); ++s)
+        if (!busy[s]) {
+            busy[s] = 1;
+            return (int)s;
+        }
+    return -1;
+}
+
+void ForkPool::release(int s) {
+    std::lock_guard<std::mutex> lock(mu);
+    busy[(size_t)s] = 0;
+}
+
+void Ctx::use_branch(const Branch &b) {
+    scratch = b.scratch;
+    scratch_bytes = b.scratch_bytes;
+    d_idx = b.d_idx;
+    idx_cap = b.idx_cap;
+    idx_used = 0;
+    trsm_w = b.trsm_w;
+    trsm_w2 = b.trsm_w2;
+    limb = b.limb;
+    limb_bytes = b.limb_bytes;
+    if (!stat_mapped) d_stat = b.d_stat;
+}
+
+// F = (k - r1) x (n - h) and G = (m - k) x (h - r1) are disjoint blocks and
+// their decompositions independent, so when both are large and a helper
+// slot is free, G runs on the slot's helper thread (its own stream, device
+// regions and pinned status words; its stream waits for the caller's work
+// so far, and the caller's stream waits for G's end) while F runs here.
+void Ctx::node_pair(const Blk &bF, Zero zF, const Blk &bG, Zero zG, int64_t &r2, int64_t &r3,
+                    std::vector<int32_t> &P2, std::vector<int32_t> &Q2, std::vector<int32_t> &P3,
+                    std::vector<int32_t> &Q3) {
+    const bool big = pool && zF != Z_ZERO && zG != Z_ZERO && std::min(bF.m, bF.n) >= pool->min_dim &&
+                     std::min(bG.m, bG.n) >= pool->min_dim;
+    const int s = big ? pool->acquire() : -1;
+    if (s < 0) {
+        r2 = node(bF.i, bF.j, bF.m, bF.n, zF, P2, Q2);
+        r3 = node(bG.i, bG.j, bG.m, bG.n, zG, P3, Q3);
+        return;
+    }
+    Ctx sub = *this;
+    sub.st = pool->stream[(size_t)s];
+    sub.stats = Stats();
+    sub.use_branch(pool->slot[(size_t)s]);
+    check(hipEventRecord(pool->ev_start[(size_t)s], st));
+    check(hipStreamWaitEvent(sub.st, pool->ev_start[(size_t)s], 0));
+    const int32_t mask = g_prof.mask;
+    KStat kst[KCLASSES];
+    std::exception_ptr sub_err;
+    Worker *helper = pool->worker[(size_t)s];
+    helper->post([&] {
+        try {
+            check(hipSetDevice(pool->dev));
+            if (!pool->bind_thread(sub)) throw DeviceError{hipErrorOutOfMemory};
+            sub.use_branch(pool->slot[(size_t)s]);
+            // this branch's sticky flags (failed speculation, base-case
+            // self-check) start cleared and are checked at its end
+            sub.h_stat[STAT_SPEC] = 0;
+            sub.h_stat[STAT_ERR] = 0;
+            if (!sub.stat_mapped)
+                check(hipMemcpyAsync(sub.d_stat + STAT_SPEC, sub.h_stat + STAT_SPEC, 2 * sizeof(int32_t),
+                                     hipMemcpyHostToDevice, sub.st));
+            g_prof.discard();
+            g_prof.mask = mask;
+            for (int c = 0; c < KCLASSES; ++c) g_prof.k[c] = KStat();
+            r3 = sub.node(bG.i, bG.j, bG.m, bG.n, zG, P3, Q3);
+            sub.read_status(STAT_SPEC, 2);
+            sub.check_err();
+            if (sub.spec && sub.h_stat[STAT_SPEC] != 0) throw SpecFail{};
+            check(hipEventRecord(pool->ev_done[(size_t)s], sub.st));
+            if (mask) {
+                check(hipStreamSynchronize(sub.st));
+                g_prof.resolve();
+            }
+            for (int c = 0; c < KCLASSES; ++c) kst[c] = g_prof.k[c];
+            g_prof.mask = 0;
+        } catch (...) {
+            sub_err = std::current_exception();
+            g_prof.discard();
+            (void)hipStreamSynchronize(sub.st);
+        }
+    });
+    try {
+        r2 = node(bF.i, bF.j, bF.m, bF.n, zF, P2, Q2);
+    } catch (...) {
+        helper->wait();
+        (void)hipStreamSynchronize(sub.st);
+        pool->release(s);
+        throw;
+    }
+    helper->wait();
+    pool->release(s);
+    if (sub_err) std::rethrow_exception(sub_err);
+    check(hipStreamWaitEvent(st, pool->ev_done[(size_t)s], 0));
+    stats.nodes += sub.stats.nodes;
+    stats.basecases += sub.stats.basecases;
+    stats.launches += sub.stats.launches;
+    stats.syncs += sub.stats.syncs;
+    opt_fails = std::max(opt_fails, sub.opt_fails);
+    for (int c = 0; c < KCLASSES; ++c) {
+        g_prof.k[c].launches += kst[c].launches;
+        g_prof.k[c].ms += kst[c].ms;
+        g_prof.k[c].flops += kst[c].flops;
+        g_prof.k[c].bytes += kst[c].bytes;
+    }
 }
 
 }  // namespace pluq

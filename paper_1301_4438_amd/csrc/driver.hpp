@@ -3,6 +3,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <condition_variable>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -67,6 +72,53 @@ constexpr int64_t STAT_ERR = 9;      // sticky flag: an ordered base case failed
 constexpr int64_t STAT_BC = 64;      // base-case status: r, ok / rpm columns
 constexpr int64_t STAT_WORDS = 64 + 2 + 16384 + 64;
 
+// Device regions of one recursion branch: every branch (the caller's and
+// each helper that runs a PLUQ(G) beside a PLUQ(F)) has its own.
+struct Branch {
+    char *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int32_t *d_idx = nullptr;
+    size_t idx_cap = 0;
+    int32_t *d_stat = nullptr;    // status words in the workspace (when host memory cannot be mapped)
+    char *trsm_w = nullptr, *trsm_w2 = nullptr;
+    char *limb = nullptr;
+    size_t limb_bytes = 0;
+};
+
+struct Ctx;
+
+// A persistent helper thread that runs one posted job at a time (its
+// thread-local pinned status words and event pool are set up once and kept).
+struct Worker {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::function<void()> job;
+    bool busy = false, quit = false;
+    Worker();
+    ~Worker();
+    void post(std::function<void()> j);
+    void wait();
+};
+
+// Helper branches of one decomposition: the independent calls PLUQ(F) and
+// PLUQ(G) of a node (Section 9's perspective) run concurrently when a slot
+// is free -- G on a helper host thread with the slot's stream and regions.
+struct ForkPool {
+    std::mutex mu;
+    std::vector<Branch> slot;
+    std::vector<hipStream_t> stream;
+    std::vector<hipEvent_t> ev_start, ev_done;
+    std::vector<Worker *> worker;
+    std::vector<char> busy;
+    int dev = 0;
+    int64_t min_dim = 256;   // F and G must both be at least this in each dimension
+    // sets up the calling (helper) thread's pinned status words in c
+    std::function<bool(Ctx &)> bind_thread;
+    int acquire();
+    void release(int s);
+};
+
 struct Ctx {
     // problem
     int dt = 0;
@@ -107,6 +159,8 @@ struct Ctx {
     int opt_fails = 0;
     // No per-launch event timing (the entry point that allocates nothing).
     bool noprof = false;
+    // Helper branches for PLUQ(F) || PLUQ(G) (null: none).
+    ForkPool *pool = nullptr;
 
     void check(hipError_t e);
     // Issue one kernel launch (f returns its hipError_t), timed when the
@@ -144,6 +198,11 @@ struct Ctx {
     void check_err();    // the error flag among the words just read back
     int64_t node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vector<int32_t> &prow,
                  std::vector<int32_t> &pcol);
+    // PLUQ(F) and PLUQ(G) of a node, concurrently when a helper slot is free
+    void node_pair(const Blk &bF, Zero zF, const Blk &bG, Zero zG, int64_t &r2, int64_t &r3,
+                   std::vector<int32_t> &P2, std::vector<int32_t> &Q2, std::vector<int32_t> &P3,
+                   std::vector<int32_t> &Q3);
+    void use_branch(const Branch &b);
 };
 
 void zorder_from_rpm(int64_t m, int64_t n, const int32_t *rpm_col, std::vector<int32_t> &prow,
