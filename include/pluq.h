@@ -103,6 +103,11 @@ typedef struct {
                                    at most 16); each branch needs its own workspace share
                                    (pluq_workspace_size counts them); the result does not
                                    depend on it */
+    int32_t in_place;           /* non-zero: a workspace linear in m + n, independent of
+                                   m n (Section 2's in-place remark): no copy of A (no
+                                   speculative attempt), one branch, permutations through
+                                   strips of 64 columns or rows, the INT8 form's digit
+                                   planes for 512-deep pieces; same result, more launches */
 } pluq_opts;
 
 /* Human-readable name of a status code (static storage). */

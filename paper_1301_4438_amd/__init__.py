@@ -42,7 +42,8 @@ class pluq_opts(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("validate_entries", ctypes.c_int32),
                 ("cutoff_override", ctypes.c_int32),
                 ("batch_panel", ctypes.c_int32), ("batch_groups", ctypes.c_int32),
-                ("no_speculation", ctypes.c_int32), ("branches", ctypes.c_int32)]
+                ("no_speculation", ctypes.c_int32), ("branches", ctypes.c_int32),
+                ("in_place", ctypes.c_int32)]
 
 
 class pluq_kernel_stat(ctypes.Structure):
@@ -154,10 +155,12 @@ def _stream(t):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _opts(form="fp64", validate=False, cutoff=0, batch_panel=0, batch_groups=0, speculate=True, branches=0):
+def _opts(form="fp64", validate=False, cutoff=0, batch_panel=0, batch_groups=0, speculate=True, branches=0,
+          in_place=False):
     o = pluq_opts()
     o.no_speculation = 0 if speculate else 1
     o.branches = int(branches)
+    o.in_place = int(bool(in_place))
     o.form = FORMS[form] if isinstance(form, str) else int(form)
     o.validate_entries = int(bool(validate))
     o.cutoff_override = int(cutoff)

@@ -63,9 +63,9 @@ int64_t fp32_kchunk(uint64_t p) {
 
 // Bytes of digit planes for the INT8-limb form of an m x n decomposition:
 // enough for one KMAX_I8-deep piece of any update (rows + columns <= m + n).
-size_t limb_bytes_for(int64_t m, int64_t n, uint64_t p) {
+size_t limb_bytes_for(int64_t m, int64_t n, uint64_t p, int64_t depth = KMAX_I8) {
     const int nl = i8_limbs((double)p);
-    const int64_t kmax = std::min<int64_t>((std::min(m, n) + 63) / 64 * 64 + 128, KMAX_I8);
+    const int64_t kmax = std::min<int64_t>((std::min(m, n) + 63) / 64 * 64 + 128, depth);
     return (size_t)nl * (size_t)(m + n) * (size_t)kmax;
 }
 
@@ -158,21 +158,31 @@ size_t trsm_w_bytes(int64_t r, size_t esz) {
     return (size_t)((r + TRSM_NB - 1) / TRSM_NB) * TRSM_NB * TRSM_NB * esz;
 }
 
+// The in-place variant: permutation strips and digit-plane depth.
+constexpr int64_t IN_PLACE_STRIP = 64;
+constexpr int64_t IN_PLACE_DEPTH = 512;
+
+bool in_place(const pluq_opts *o) { return o && o->in_place; }
+
 int branches_for(int64_t m, int64_t n, const pluq_opts *o) {
-    if (std::min(m, n) < 2 * FORK_MIN_DIM) return 1;
+    if (std::min(m, n) < 2 * FORK_MIN_DIM || in_place(o)) return 1;
     const int b = (o && o->branches > 0) ? o->branches : DEFAULT_BRANCHES;
     return std::min(b, 16);
 }
 
-Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec, int nbranch) {
+Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec, int nbranch, bool inplace) {
     Layout L;
     L.idx_elems = (size_t)(4 * (m + n) + 65536);
     const size_t full = (size_t)m * (size_t)n * esz;
-    const size_t strip = (size_t)64 * (size_t)std::max<int64_t>(std::max<int64_t>(m, n), 1) * esz;
-    L.scratch_bytes = std::max(std::min(full, (size_t)256 << 20), std::min(full, strip));
+    const size_t strip = (size_t)IN_PLACE_STRIP * (size_t)std::max<int64_t>(std::max<int64_t>(m, n), 1) * esz;
+    // permutations go through strips of this scratch (at least one 64-wide
+    // strip of the largest block; 256 MiB unless in place)
+    L.scratch_bytes = inplace ? std::min(full, strip) : std::max(std::min(full, (size_t)256 << 20), std::min(full, strip));
     if (L.scratch_bytes == 0) L.scratch_bytes = ALIGN;
     L.w_bytes = trsm_w_bytes(std::min(m, n), esz);
-    L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0) ? limb_bytes_for(m, n, p) : 0;
+    L.limb_bytes = (form == PLUQ_FORM_INT8 && m > 0 && n > 0)
+                       ? limb_bytes_for(m, n, p, inplace ? IN_PLACE_DEPTH : KMAX_I8) : 0;
+    if (inplace) spec = false;
     L.stat_off = 0;
     L.idx_off = align_up(STAT_WORDS * sizeof(int32_t));
     L.w_off = L.idx_off + align_up(L.idx_elems * sizeof(int32_t));
@@ -372,7 +382,7 @@ const char *pluq_last_error(void) { return g_err; }
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
     return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64, !(opts && opts->no_speculation),
-                  branches_for(m, n, opts)).total;
+                  branches_for(m, n, opts), in_place(opts)).total;
 }
 
 pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
@@ -386,7 +396,8 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
     const int form = opts ? opts->form : PLUQ_FORM_FP64;
     if ((s = form_check(form, p)) != PLUQ_OK) return s;
     const size_t esz = esize(dt);
-    const Layout L = layout(m, n, esz, p, form, !(opts && opts->no_speculation), branches_for(m, n, opts));
+    const Layout L = layout(m, n, esz, p, form, !(opts && opts->no_speculation), branches_for(m, n, opts),
+                            in_place(opts));
     if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
     if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
 

@@ -99,3 +99,18 @@ def test_form_bounds_host_checks():
     assert w8 >= w64 + 2 * 2048 * 1024
     assert L.pluq_modmm_workspace_size(100, 200, 5000, 1) >= 2 * 300 * 4096
     assert L.pluq_modmm_workspace_size(100, 200, 5000, 0) == 0
+
+
+def test_in_place_workspace_is_linear():
+    """The in-place variant's workspace is linear in m + n (no copy of A, one
+    branch, 64-wide permutation strips, 512-deep digit planes): doubling both
+    dimensions at most doubles it (plus constants), while the default
+    workspace grows with m n."""
+    def ws(m, n, form, in_place):
+        return pl.pluq_workspace_size(m, n, 1, 65521, pl._opts(form, in_place=in_place))
+    for form in ("fp64", "int8"):
+        a, b = ws(8192, 8192, form, True), ws(16384, 16384, form, True)
+        assert b <= 2 * a + (1 << 20)
+        assert ws(16384, 16384, form, True) * 8 < ws(16384, 16384, form, False)
+        # at most a fixed number of bytes per row and column
+        assert b <= 16384 * 2 * (64 * 8 + 2 * 512 + 16 + 2 * 64 * 8) + (4 << 20)

@@ -46,3 +46,27 @@ def test_branches_equal_oracle(gpu_lib, name):
                 assert r == ro
                 assert np.array_equal(P.cpu().numpy(), Po) and np.array_equal(Q.cpu().numpy(), Qo)
                 assert np.array_equal(X.cpu().numpy().astype(np.int64), Xo)
+
+
+@pytest.mark.parametrize("name", [c[0] for c in CASES])
+def test_in_place_equals_oracle(gpu_lib, name):
+    """The in-place variant (workspace linear in m + n) gives the oracle's
+    result in every form."""
+    import torch
+    build, p = {c[0]: (c[1], c[2]) for c in CASES}[name]
+    A = build()
+    Po, Qo, ro, Xo = oracle.pluqz(A, p)
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).to(torch.float64).cuda()
+    for form in (["fp64", "int8", "fp32"] if p < 2048 else ["fp64", "int8"]):
+        note(name, "in place", form)
+        X = Ad.clone()
+        P = torch.empty(A.shape[0], dtype=torch.int64, device="cuda")
+        Q = torch.empty(A.shape[1], dtype=torch.int64, device="cuda")
+        o = gpu_lib._opts(form, in_place=True)
+        ws = torch.empty(gpu_lib.pluq_workspace_size(A.shape[0], A.shape[1], 1, p, o), dtype=torch.uint8,
+                         device="cuda")
+        r = gpu_lib.pluq_modp(X, p, P, Q, o, ws)
+        torch.cuda.synchronize()
+        assert r == ro
+        assert np.array_equal(P.cpu().numpy(), Po) and np.array_equal(Q.cpu().numpy(), Qo)
+        assert np.array_equal(X.cpu().numpy().astype(np.int64), Xo)

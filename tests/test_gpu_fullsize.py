@@ -124,6 +124,17 @@ def test_c4_16384_forms(gpu_lib, p):
         Pf, Qf, rf, Xf = _decompose(gpu_lib, A, p, f)
         assert rf == r and torch.equal(Pf, P) and torch.equal(Qf, Q) and torch.equal(Xf, X)
         del Xf
+    # the in-place variant (workspace linear in m + n) of the INT8 form
+    note("c4 in place", p)
+    Xi = A.clone()
+    Pi = torch.empty(n, dtype=torch.int64, device="cuda")
+    Qi = torch.empty(n, dtype=torch.int64, device="cuda")
+    o = gpu_lib._opts("int8", in_place=True)
+    ws = torch.empty(gpu_lib.pluq_workspace_size(n, n, 1, p, o), dtype=torch.uint8, device="cuda")
+    ri = gpu_lib.pluq_modp(Xi, p, Pi, Qi, o, ws)
+    torch.cuda.synchronize()
+    assert ri == r and torch.equal(Pi, P) and torch.equal(Qi, Q) and torch.equal(Xi, X)
+    del Xi, ws
     assert structure_torch(P, Q, r, X)
 
 
