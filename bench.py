@@ -387,6 +387,13 @@ def comparisons(pl, A65521, seed):
     return out
 
 
+def tuning_used(pl, p, m, n):
+    """The tuning-table parameters the headline call ran with (INT8 form,
+    float64 storage) and whether they came from the tuner's cache."""
+    params, hit = pl.tune_get(pl.FORMS["int8"], p, 1, m, n)
+    return {"params": params, "from_tune_cache": hit}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -443,6 +450,7 @@ def main():
         "device_ms_per_class_in_profiled_step": {c: round(v["ms"], 3) for c, v in prof.items() if v["launches"]},
         "launches_per_class_in_profiled_step": {c: v["launches"] for c, v in prof.items() if v["launches"]},
         "library_stats_last_call": stats,
+        "tuning": tuning_used(pl, p, m, n),
     }
     if not args.no_comparisons:
         out["comparisons"] = comparisons(pl, A, args.seed)

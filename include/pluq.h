@@ -222,6 +222,35 @@ pluq_status pluq_modp_batched(int64_t batch, const int64_t *m, const int64_t *n,
                               int64_t *d_r, const pluq_opts *opts, void *dWork,
                               size_t work_bytes, void *stream);
 
+/* ---- tuning (performance only: no parameter changes any result) ----
+ *
+ * A process-wide table of tuned parameters, filled by the project's tuner
+ * (paper_1301_4438_amd/tune.py writes a cache that the Python binding
+ * loads).  An entry is keyed by (form, p class, element type, shape bucket):
+ * form a pluq_form, or 3 for the batched form; p class 0 for p <= 256, 1 for
+ * p <= 65536, 2 above; bucket floor(log2(min(m, n))) (0 for the batched
+ * form); -1 in a key matches anything, and the most specific matching entry
+ * wins.  A
+ * zero field means the built-in default; explicit pluq_opts fields
+ * (cutoff_override, batch_panel, batch_groups) take precedence.
+ */
+typedef struct {
+    int32_t mm_tiles128;   /* an MM launch uses 128 x 128 tiles from this many such tiles on (0: 240) */
+    int32_t mm_tiles64;    /* else 64 x 64 tiles from this many on, else 32 x 32 (0: 192) */
+    int32_t cutoff;        /* base-case tile dimension, 16 .. 128 (0: 128) */
+    int32_t fork_min_dim;  /* PLUQ(F) || PLUQ(G) when both are at least this (0: 256) */
+    int64_t i8_min_work;   /* INT8 form: updates below this many multiply-adds stay in FP64 (0: 2^26) */
+    int32_t batch_panel;   /* batched form: panel width 8 or 16 (0: 8) */
+    int32_t batch_groups;  /* batched form: work-groups per compute unit (0: 4 for panel 8, 2 for 16) */
+} pluq_tune;
+
+pluq_status pluq_tune_set(int32_t form, int32_t pclass, int32_t dtype, int32_t bucket, const pluq_tune *t);
+void pluq_tune_clear(void);
+/* The parameters a call with these arguments uses (defaults filled in);
+ * returns 1 in *from_table when a table entry matched, else 0. */
+pluq_status pluq_tune_get(int32_t form, uint64_t p, int32_t dtype, int64_t m, int64_t n, pluq_tune *out,
+                          int32_t *from_table);
+
 /* ---- outputs read off a decomposition by permutation (Sections 3, 4) ----
  *
  * All take the result of pluq_modp -- the packed X = [L\U V; M 0] (m x n,

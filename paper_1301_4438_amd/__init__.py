@@ -46,6 +46,17 @@ class pluq_opts(ctypes.Structure):
                 ("in_place", ctypes.c_int32)]
 
 
+class pluq_tune(ctypes.Structure):
+    _fields_ = [("mm_tiles128", ctypes.c_int32), ("mm_tiles64", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("fork_min_dim", ctypes.c_int32), ("i8_min_work", ctypes.c_int64), ("batch_panel", ctypes.c_int32),
+                ("batch_groups", ctypes.c_int32)]
+
+
+TUNE_FIELDS = [f for f, _ in pluq_tune._fields_]
+TUNE_FORM_BATCHED = 3
+TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
 class pluq_kernel_stat(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("flops", ctypes.c_double),
                 ("bytes", ctypes.c_double)]
@@ -111,6 +122,12 @@ def load():
     L.pluq_leading_rank_profiles_device.restype = ctypes.c_int
     L.pluq_leading_rank_profiles_device.argtypes = [_i64, _i64, _i64, _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp,
                                                     ctypes.c_size_t, _vp]
+    L.pluq_tune_set.restype = ctypes.c_int
+    L.pluq_tune_set.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    L.pluq_tune_clear.restype = None
+    L.pluq_tune_clear.argtypes = []
+    L.pluq_tune_get.restype = ctypes.c_int
+    L.pluq_tune_get.argtypes = [ctypes.c_int32, _u64, ctypes.c_int32, _i64, _i64, ctypes.c_void_p, ctypes.c_void_p]
     L.pluq_modmm_noalloc.restype = ctypes.c_int
     L.pluq_modmm_noalloc.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                                      ctypes.c_int32, _vp]
@@ -126,6 +143,8 @@ def load():
     L.pluq_last_stats.restype = None
     L.pluq_last_stats.argtypes = [_i64p, _i64p, _i64p, _i64p]
     _lib = L
+    if os.environ.get("PLUQ_NO_TUNE_CACHE") != "1":
+        load_tune_cache()
     return L
 
 
@@ -195,6 +214,44 @@ def _workspace(device, nbytes):
 
 
 # ------------------------------------------------------------ C ABI names --
+
+def tune_set(form, pclass, dtype, bucket, **params):
+    """Register tuned parameters for a key (form code or 3 for the batched
+    form, p class, element type code, shape bucket; -1 matches anything)."""
+    t = pluq_tune()
+    for k, v in params.items():
+        setattr(t, k, int(v))
+    _check(load().pluq_tune_set(int(form), int(pclass), int(dtype), int(bucket), ctypes.byref(t)), "pluq_tune_set")
+
+
+def tune_clear():
+    load().pluq_tune_clear()
+
+
+def tune_get(form, p, dtype, m, n):
+    """(parameters a call with these arguments uses, whether a table entry matched)."""
+    t = pluq_tune()
+    hit = ctypes.c_int32(0)
+    _check(load().pluq_tune_get(int(form), int(p), int(dtype), int(m), int(n), ctypes.byref(t), ctypes.byref(hit)),
+           "pluq_tune_get")
+    return {f: getattr(t, f) for f in TUNE_FIELDS}, bool(hit.value)
+
+
+def load_tune_cache(path=None):
+    """Register the entries of the tuner's cache (gfx950 entries only).
+    Returns the number of entries registered."""
+    import json
+    path = path or TUNE_CACHE
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        cache = json.load(f)
+    if cache.get("arch") != "gfx950":
+        return 0
+    for e in cache.get("entries", []):
+        tune_set(e["form"], e["pclass"], e["dtype"], e["bucket"], **e["params"])
+    return len(cache.get("entries", []))
+
 
 def pluq_status_string(status: int) -> str:
     return load().pluq_status_string(int(status)).decode()

@@ -276,6 +276,61 @@ pluq_status form_check(int form, uint64_t p) {
 }
 
 
+
+// --------------------------------------------------------------- tuning --
+
+struct TuneEntry {
+    int32_t form, pclass, dtype, bucket;
+    pluq_tune t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+int pclass_of(uint64_t p) { return p <= 256 ? 0 : (p <= 65536 ? 1 : 2); }
+
+constexpr int32_t TUNE_FORM_BATCHED = 3;   // tuning key of the batched form
+
+int bucket_of(int64_t m, int64_t n) {
+    int64_t d = std::max<int64_t>(std::min(m, n), 1);
+    int b = 0;
+    while (d > 1 && b < 31) {
+        d >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+// The effective parameters: the most specific matching entry, defaults for
+// its zero fields.
+pluq_tune tune_for(int32_t form, uint64_t p, int32_t dtype, int64_t m, int64_t n, bool *hit) {
+    pluq_tune t;
+    std::memset(&t, 0, sizeof(t));
+    const int pc = pclass_of(p), b = bucket_of(m, n);
+    int best = -1;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const TuneEntry &e : g_tune) {
+            if ((e.form >= 0 && e.form != form) || (e.pclass >= 0 && e.pclass != pc) ||
+                (e.dtype >= 0 && e.dtype != dtype) || (e.bucket >= 0 && e.bucket != b))
+                continue;
+            const int spec = (e.form >= 0) + (e.pclass >= 0) + (e.dtype >= 0) + (e.bucket >= 0);
+            if (spec > best) {
+                best = spec;
+                t = e.t;
+            }
+        }
+    }
+    if (hit) *hit = best >= 0;
+    if (t.mm_tiles128 <= 0) t.mm_tiles128 = 240;
+    if (t.mm_tiles64 <= 0) t.mm_tiles64 = 192;
+    if (t.cutoff <= 0) t.cutoff = 128;
+    if (t.fork_min_dim <= 0) t.fork_min_dim = (int32_t)FORK_MIN_DIM;
+    if (t.i8_min_work <= 0) t.i8_min_work = (int64_t)I8_MIN_WORK;
+    if (t.batch_panel != 8 && t.batch_panel != 16) t.batch_panel = 8;
+    if (t.batch_groups <= 0 || t.batch_groups > 8) t.batch_groups = t.batch_panel == 8 ? 4 : 2;
+    return t;
+}
+
 // ---------------------------------------------------- MM building block --
 
 pluq_status modmm_check(int64_t m, int64_t n, int64_t k, const void *dC, int64_t ldc, const void *dA, int64_t lda,
@@ -317,6 +372,9 @@ pluq_status modmm_run(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, co
         c.kchunk32 = (int)fp32_kchunk(p);
         c.st = (hipStream_t)stream;
         c.noprof = noprof;
+        const pluq_tune tp = tune_for(form, p, (int32_t)dt, m, n, nullptr);
+        c.mm_t128 = tp.mm_tiles128;
+        c.mm_t64 = tp.mm_tiles64;
         if (form == PLUQ_FORM_INT8) {
             // the kernel-level entry always takes the int8 path
             c.limb = limb;
@@ -413,7 +471,11 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.kchunk32 = (int)fp32_kchunk(p);
         c.cap = bc_cap();
         if (c.cap <= 0) return PLUQ_ERR_DEVICE;
-        if (opts && opts->cutoff_override > 0) c.cap = std::min<int64_t>(c.cap, opts->cutoff_override);
+        const pluq_tune tp = tune_for(form, p, (int32_t)dt, m, n, nullptr);
+        c.mm_t128 = tp.mm_tiles128;
+        c.mm_t64 = tp.mm_tiles64;
+        c.i8_min_work = (double)tp.i8_min_work;
+        c.cap = std::min<int64_t>(c.cap, (opts && opts->cutoff_override > 0) ? opts->cutoff_override : tp.cutoff);
         c.A = (char *)dA;
         c.lda = lda;
         c.st = (hipStream_t)stream;
@@ -433,7 +495,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             c.check(hipGetDevice(&dev));
             if (!helpers_ready(dev, (size_t)L.nbranch - 1)) return PLUQ_ERR_DEVICE;
             pool.dev = dev;
-            pool.min_dim = FORK_MIN_DIM;
+            pool.min_dim = tp.fork_min_dim;
             for (int b = 1; b < L.nbranch; ++b) {
                 pool.slot.push_back(branch_at(w, L, b));
                 pool.stream.push_back(g_help.stream[(size_t)b - 1]);
@@ -649,8 +711,12 @@ pluq_status pluq_batched_run(int64_t batch, pluq_dtype dt, uint64_t p, const plu
     if (batch == 0) return PLUQ_OK;
     if (!dWork || (uintptr_t)dWork % ALIGN || work_bytes < align_up((size_t)batch * sizeof(BatchDesc)))
         return PLUQ_ERR_ARG;
-    const int kb = (opts && opts->batch_panel) ? opts->batch_panel : 8;
-    const int per_cu = (opts && opts->batch_groups) ? opts->batch_groups : (kb == 8 ? 4 : 2);
+    // explicit options, else the tuned entry of the batched form (key form 3)
+    const pluq_tune tb = tune_for(TUNE_FORM_BATCHED, p, (int32_t)dt, 0, 0, nullptr);
+    const int kb = (opts && opts->batch_panel) ? opts->batch_panel : tb.batch_panel;
+    const int per_cu = (opts && opts->batch_groups) ? opts->batch_groups
+                                                     : ((opts && opts->batch_panel && opts->batch_panel != tb.batch_panel)
+                                                            ? (kb == 8 ? 4 : 2) : tb.batch_groups);
     if ((kb != 8 && kb != 16) || per_cu < 1 || per_cu > 8) return PLUQ_ERR_ARG;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -947,6 +1013,40 @@ pluq_status pluq_leading_rank_profiles_device(int64_t m, int64_t n, int64_t r, c
         set_err("pluq_leading_rank_profiles_device: HIP call", e.e);
         return PLUQ_ERR_DEVICE;
     }
+    return PLUQ_OK;
+}
+
+pluq_status pluq_tune_set(int32_t form, int32_t pclass, int32_t dtype, int32_t bucket, const pluq_tune *t) {
+    if (!t || form < -1 || form > TUNE_FORM_BATCHED || pclass < -1 || pclass > 2 || dtype < -1 || dtype > 2 ||
+        bucket < -1 ||
+        bucket > 31)
+        return PLUQ_ERR_ARG;
+    if (t->cutoff < 0 || t->cutoff > 128 || (t->cutoff > 0 && t->cutoff < 16) || t->mm_tiles128 < 0 ||
+        t->mm_tiles64 < 0 || t->fork_min_dim < 0 || t->i8_min_work < 0 ||
+        (t->batch_panel != 0 && t->batch_panel != 8 && t->batch_panel != 16) || t->batch_groups < 0 ||
+        t->batch_groups > 8)
+        return PLUQ_ERR_ARG;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (TuneEntry &e : g_tune)
+        if (e.form == form && e.pclass == pclass && e.dtype == dtype && e.bucket == bucket) {
+            e.t = *t;
+            return PLUQ_OK;
+        }
+    g_tune.push_back(TuneEntry{form, pclass, dtype, bucket, *t});
+    return PLUQ_OK;
+}
+
+void pluq_tune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+}
+
+pluq_status pluq_tune_get(int32_t form, uint64_t p, int32_t dtype, int64_t m, int64_t n, pluq_tune *out,
+                          int32_t *from_table) {
+    if (!out || m < 0 || n < 0) return PLUQ_ERR_ARG;
+    bool hit = false;
+    *out = tune_for(form, p, dtype, m, n, &hit);
+    if (from_table) *from_table = hit ? 1 : 0;
     return PLUQ_OK;
 }
 

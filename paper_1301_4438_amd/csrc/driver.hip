@@ -186,7 +186,7 @@ void Ctx::mm(MMProblem *probs, int n) {
         for (int q = 0; q < live; ++q) {
             const MMProblem &pb = probs[q];
             const int64_t K = (int64_t)std::max(pb.K[0], 0) + std::max(pb.K[1], 0);
-            const bool big = pb.M >= 128 && pb.N >= 128 && K >= 128 && (double)pb.M * pb.N * K >= I8_MIN_WORK;
+            const bool big = pb.M >= 128 && pb.N >= 128 && K >= 128 && (double)pb.M * pb.N * K >= i8_min_work;
             if (!(big && mm_i8(pb))) probs[rest++] = pb;
         }
         live = rest;
@@ -203,9 +203,11 @@ void Ctx::mm(MMProblem *probs, int n) {
         }
     }
     if (form == PLUQ_FORM_FP32)
-        launch(K_MODMM, flops, bytes * (double)esz, [&] { return launch_modmm_f32(dt, probs, live, (double)p, kchunk32, st); });
+        launch(K_MODMM, flops, bytes * (double)esz,
+               [&] { return launch_modmm_f32(dt, probs, live, (double)p, kchunk32, mm_t128, mm_t64, st); });
     else
-        launch(K_MODMM, flops, bytes * (double)esz, [&] { return launch_modmm_f64(dt, probs, live, (double)p, kchunk, st); });
+        launch(K_MODMM, flops, bytes * (double)esz,
+               [&] { return launch_modmm_f64(dt, probs, live, (double)p, kchunk, mm_t128, mm_t64, st); });
 }
 
 // One update in the INT8-limb form: the inner dimension (both operand pairs)

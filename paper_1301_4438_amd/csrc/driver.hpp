@@ -142,6 +142,9 @@ struct Ctx {
     char *limb = nullptr;            // digit planes of the INT8-limb form (or null)
     size_t limb_bytes = 0;
     int kchunk32 = 0;                // FP32 form: products between reductions
+    // tuned parameters (performance only)
+    int mm_t128 = 240, mm_t64 = 192;    // MM tile choice thresholds
+    double i8_min_work = I8_MIN_WORK;  // INT8 form: smaller updates stay in FP64
     // pinned host mirrors
     int32_t *h_idx = nullptr;
     int32_t *h_stat = nullptr;

@@ -228,7 +228,8 @@ static hipError_t launch_dt(MMArgs &args, int bm, int bn, int total, hipStream_t
 }
 
 template <typename CT>
-static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
+static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p, int kchunk, int t128, int t64,
+                               hipStream_t st) {
     if (kchunk < 16 || kchunk % 16) return hipErrorInvalidValue;   // RED16 covers 16 products at a time
     MMArgs args;
     int n = 0;
@@ -247,11 +248,12 @@ static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p,
     if (n == 0) return hipSuccess;
     // Large updates use 128 x 128 tiles; smaller ones 64 x 64, and the small
     // updates of the deep recursion (fewer 64-tiles than compute units) 32 x
-    // 32, so that more compute units share their matrix-core work.  An
+    // 32, so that more compute units share their matrix-core work (the tile
+    // counts where the choice changes are tuned, 240 and 192 by default).  An
     // in-place update keeps 64 along the dimension it shares with C.
     int bm, bn;
-    if (tiles128 >= 240) bm = bn = 128;
-    else if (tiles64 >= 192 || inplace == 3) bm = bn = 64;
+    if (tiles128 >= t128) bm = bn = 128;
+    else if (tiles64 >= t64 || inplace == 3) bm = bn = 64;
     else {
         bm = (inplace & 1) ? 64 : 32;
         bn = (inplace & 2) ? 64 : 32;
@@ -278,12 +280,14 @@ static hipError_t launch_modmm(int dtype, MMProblem *probs, int nprob, double p,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
-    return launch_modmm<double>(dtype, probs, nprob, p, kchunk, st);
+hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk, int t128, int t64,
+                            hipStream_t st) {
+    return launch_modmm<double>(dtype, probs, nprob, p, kchunk, t128, t64, st);
 }
 
-hipError_t launch_modmm_f32(int dtype, MMProblem *probs, int nprob, double p, int kchunk, hipStream_t st) {
-    return launch_modmm<float>(dtype, probs, nprob, p, kchunk, st);
+hipError_t launch_modmm_f32(int dtype, MMProblem *probs, int nprob, double p, int kchunk, int t128, int t64,
+                            hipStream_t st) {
+    return launch_modmm<float>(dtype, probs, nprob, p, kchunk, t128, t64, st);
 }
 
 }  // namespace pluq

@@ -34,12 +34,14 @@ struct MMProblem {
 constexpr int MM_MAX_PROBLEMS = 4;
 
 // FP64 matrix-core form.  kchunk: number of inner-dimension terms that may
-// be accumulated before a reduction (multiple of 16, >= 16).
-hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
+// be accumulated before a reduction (multiple of 16, >= 16).  t128 / t64:
+// the launch takes 128 x 128 tiles from t128 such tiles on, else 64 x 64
+// from t64 on, else 32 x 32 (tuning only).
+hipError_t launch_modmm_f64(int dtype, MMProblem *probs, int nprob, double p, int kchunk, int t128, int t64,
                             hipStream_t st);
 // FP32 matrix-core form (p < 2^11): kchunk products between reductions,
 // kchunk * (p/2)^2 + p < 2^24.
-hipError_t launch_modmm_f32(int dtype, MMProblem *probs, int nprob, double p, int kchunk,
+hipError_t launch_modmm_f32(int dtype, MMProblem *probs, int nprob, double p, int kchunk, int t128, int t64,
                             hipStream_t st);
 
 // INT8-limb form (p <= 65536).  Number of signed 8-bit digits per operand

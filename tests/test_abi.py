@@ -114,3 +114,58 @@ def test_in_place_workspace_is_linear():
         assert ws(16384, 16384, form, True) * 8 < ws(16384, 16384, form, False)
         # at most a fixed number of bytes per row and column
         assert b <= 16384 * 2 * (64 * 8 + 2 * 512 + 16 + 2 * 64 * 8) + (4 << 20)
+
+
+def test_tuning_table_lookup():
+    """Most specific entry wins, zero fields take the defaults, wildcards (-1)
+    match anything, bad parameters are refused, and clearing restores the
+    defaults."""
+    pl.tune_clear()
+    try:
+        d, hit = pl.tune_get(0, 65521, 1, 4096, 4096)
+        assert not hit and d["cutoff"] == 128 and d["mm_tiles128"] == 240 and d["batch_panel"] == 8
+        pl.tune_set(-1, -1, -1, -1, mm_tiles64=100)
+        pl.tune_set(0, 1, 1, 12, cutoff=96, mm_tiles128=300)
+        t, hit = pl.tune_get(0, 65521, 1, 4096, 8192)     # bucket of min(m, n) = 12
+        assert hit and t["cutoff"] == 96 and t["mm_tiles128"] == 300 and t["mm_tiles64"] == 192
+        t, hit = pl.tune_get(0, 65521, 1, 8192, 8192)     # bucket 13: only the wildcard matches
+        assert hit and t["cutoff"] == 128 and t["mm_tiles64"] == 100
+        t, hit = pl.tune_get(1, 251, 1, 4096, 4096)
+        assert hit and t["mm_tiles64"] == 100
+        pl.tune_set(0, 1, 1, 12, cutoff=64)                # replaces the entry
+        t, _ = pl.tune_get(0, 65521, 1, 4096, 4096)
+        assert t["cutoff"] == 64 and t["mm_tiles128"] == 240
+        pl.tune_set(pl.TUNE_FORM_BATCHED, -1, 2, -1, batch_panel=16)
+        t, _ = pl.tune_get(pl.TUNE_FORM_BATCHED, 65521, 2, 0, 0)
+        assert t["batch_panel"] == 16 and t["batch_groups"] == 2
+        for bad in (dict(cutoff=8), dict(cutoff=256), dict(batch_panel=12), dict(batch_groups=9),
+                    dict(i8_min_work=-1)):
+            with pytest.raises(pl.PluqError):
+                pl.tune_set(0, 1, 1, 12, **bad)
+        with pytest.raises(pl.PluqError):
+            pl.tune_set(4, 1, 1, 12, cutoff=64)
+        pl.tune_clear()
+        assert not pl.tune_get(0, 65521, 1, 4096, 4096)[1]
+    finally:
+        pl.tune_clear()
+        pl.load_tune_cache()
+
+
+def test_tune_cache_well_formed():
+    """The committed tuner output (when present) is for gfx950 and every entry
+    is accepted by pluq_tune_set."""
+    import json
+    if not os.path.exists(pl.TUNE_CACHE):
+        pytest.skip("no tuner output committed")
+    with open(pl.TUNE_CACHE) as f:
+        cache = json.load(f)
+    assert cache["arch"] == "gfx950" and cache["entries"]
+    pl.tune_clear()
+    try:
+        assert pl.load_tune_cache() == len(cache["entries"])
+        for e in cache["entries"]:
+            assert set(e) >= {"form", "pclass", "dtype", "bucket", "params"}
+            assert set(e["params"]) <= set(pl.TUNE_FIELDS)
+    finally:
+        pl.tune_clear()
+        pl.load_tune_cache()
