@@ -242,6 +242,11 @@ typedef struct {
     int64_t i8_min_work;   /* INT8 form: updates below this many multiply-adds stay in FP64 (0: 2^26) */
     int32_t batch_panel;   /* batched form: panel width 8 or 16 (0: 8) */
     int32_t batch_groups;  /* batched form: work-groups per compute unit (0: 4 for panel 8, 2 for 16) */
+    int32_t strassen_min;  /* FP64 / FP32 forms: an MM update of the recursion whose three dimensions
+                              are all at least this takes one level of Winograd's 7-product scheme
+                              (>= 128; 0: 4096; a value above every dimension turns it off).  The
+                              workspace holds it only when min(m, n) >= 2 * strassen_min at the time
+                              of the size query; a smaller workspace keeps the classical update. */
 } pluq_tune;
 
 pluq_status pluq_tune_set(int32_t form, int32_t pclass, int32_t dtype, int32_t bucket, const pluq_tune *t);
@@ -343,6 +348,28 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
                        size_t work_bytes, void *stream);
 
 /*
+ * MM(C, A, B) with one level of Winograd's form of Strassen's product: the
+ * sub-cubic matrix product that Section 5's O(m n r^(omega-2)) bound counts
+ * on.  A, B and C are cut into 2 x 2 blocks of floor(m/2) x floor(k/2),
+ * floor(k/2) x floor(n/2) and floor(m/2) x floor(n/2); the 7 block products
+ * run on the matrix cores of `form` (PLUQ_FORM_FP64 or PLUQ_FORM_FP32; the
+ * INT8 form is PLUQ_ERR_UNSUPPORTED), the 8 operand sums and the output
+ * combinations are reduced to canonical residues, and a last row, column or
+ * inner index left over by odd sizes is updated classically.  Every
+ * operation is exact mod p, so C ends bit-identical to pluq_modmm's.
+ * Same arguments as pluq_modmm; dWork holds the block sums and two block
+ * products: pluq_modmm_winograd_workspace_size(m, n, k, dt) bytes, 256-byte
+ * aligned.  m, n and k must be at least 2 (else PLUQ_ERR_ARG).
+ * Asynchronous on `stream`.  pluq_modp applies the same scheme to the large
+ * updates of its recursion (pluq_tune.strassen_min).
+ */
+size_t pluq_modmm_winograd_workspace_size(int64_t m, int64_t n, int64_t k, pluq_dtype dt);
+pluq_status pluq_modmm_winograd(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc,
+                                const void *dA, int64_t lda, const void *dB, int64_t ldb,
+                                pluq_dtype dt, uint64_t p, int32_t form, void *dWork,
+                                size_t work_bytes, void *stream);
+
+/*
  * pluq_modmm without a workspace argument and without allocating anything,
  * for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
@@ -412,7 +439,8 @@ enum {
     PLUQ_K_MODMM_I8 = 6,  /* INT8 form: limb GEMMs of the large MM updates */
     PLUQ_K_TRSM_DIAG = 7, /* triangular solves: inversion of the 64 x 64 diagonal blocks */
     PLUQ_K_BASECASE_RPM = 8, /* base case: rank-profile search of a non-generic tile */
-    PLUQ_K_COUNT = 9
+    PLUQ_K_LINCOMB = 9,   /* Winograd's block sums and output combinations */
+    PLUQ_K_COUNT = 10
 };
 typedef struct {
     int64_t launches;

@@ -18,7 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpluq.so")
 
 PLUQ_OK = 0
+PLUQ_ERR_ARG = 1
 PLUQ_ERR_UNSUPPORTED = 4
+PLUQ_ERR_WORKSPACE = 7
 STATUS = {0: "ok", 1: "invalid argument", 2: "modulus outside [2, 2^26)", 3: "entry outside [0, p)",
           4: "form cannot be exact for this modulus", 5: "host allocation failed",
           6: "device (HIP) error", 7: "workspace too small"}
@@ -49,7 +51,7 @@ class pluq_opts(ctypes.Structure):
 class pluq_tune(ctypes.Structure):
     _fields_ = [("mm_tiles128", ctypes.c_int32), ("mm_tiles64", ctypes.c_int32), ("cutoff", ctypes.c_int32),
                 ("fork_min_dim", ctypes.c_int32), ("i8_min_work", ctypes.c_int64), ("batch_panel", ctypes.c_int32),
-                ("batch_groups", ctypes.c_int32)]
+                ("batch_groups", ctypes.c_int32), ("strassen_min", ctypes.c_int32)]
 
 
 TUNE_FIELDS = [f for f, _ in pluq_tune._fields_]
@@ -63,7 +65,7 @@ class pluq_kernel_stat(ctypes.Structure):
 
 
 KERNEL_CLASSES = ["modmm", "trsm_leaf", "perm", "basecase", "scan", "limb", "modmm_i8", "trsm_diag",
-                  "basecase_rpm"]
+                  "basecase_rpm", "lincomb"]
 
 
 def load():
@@ -106,6 +108,11 @@ def load():
     L.pluq_batched_run.argtypes = [_i64, ctypes.c_int, _u64, ctypes.POINTER(pluq_opts), _vp, ctypes.c_size_t, _vp]
     L.pluq_modmm_workspace_size.restype = ctypes.c_size_t
     L.pluq_modmm_workspace_size.argtypes = [_i64, _i64, _i64, ctypes.c_int32]
+    L.pluq_modmm_winograd_workspace_size.restype = ctypes.c_size_t
+    L.pluq_modmm_winograd_workspace_size.argtypes = [_i64, _i64, _i64, ctypes.c_int]
+    L.pluq_modmm_winograd.restype = ctypes.c_int
+    L.pluq_modmm_winograd.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
+                                      ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
     L.pluq_modmm.restype = ctypes.c_int
     L.pluq_modmm.argtypes = [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, ctypes.c_int, _u64,
                              ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
@@ -408,6 +415,30 @@ def pluq_modmm(C, A, B, p: int, form="fp64", work=None):
                       ctypes.c_void_p(work.data_ptr() if work is not None else 0),
                       work.numel() if work is not None else 0, _stream(C))
     _check(st, "pluq_modmm")
+
+
+def pluq_modmm_winograd(C, A, B, p: int, form="fp64", work=None):
+    """C <- C - A B mod p by one level of Winograd's scheme (FP64 or FP32
+    form; m, n, k >= 2), in place and asynchronous."""
+    L = load()
+    m, n = C.shape
+    k = A.shape[1]
+    if tuple(A.shape) != (m, k) or tuple(B.shape) != (k, n):
+        raise ValueError(f"shape mismatch: C {tuple(C.shape)}, A {tuple(A.shape)}, B {tuple(B.shape)}")
+    if A.dtype != C.dtype or B.dtype != C.dtype:
+        raise TypeError("A, B and C must share one element type")
+    for t in (A, B, C):
+        if t.dim() != 2 or (t.shape[1] > 1 and t.stride(1) != 1):
+            raise ValueError("operands must be row-major 2-D tensors with unit column stride")
+    dt = _dtype_code(C)
+    fcode = FORMS[form] if isinstance(form, str) else int(form)
+    need = int(L.pluq_modmm_winograd_workspace_size(m, n, k, dt))
+    if work is None:
+        work = _workspace(C.device, max(need, 256))
+    st = L.pluq_modmm_winograd(m, n, k, ctypes.c_void_p(C.data_ptr()), _ld(C), ctypes.c_void_p(A.data_ptr()),
+                               _ld(A), ctypes.c_void_p(B.data_ptr()), _ld(B), dt, p, fcode,
+                               ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(C))
+    _check(st, "pluq_modmm_winograd")
 
 
 def _ptr(t):

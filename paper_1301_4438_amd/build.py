@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libpluq.so")
 BUILD = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_modmm.hip", "k_modmm_i8.hip", "k_batched.hip", "k_trsm.hip", "k_perm.hip", "k_basecase.hip", "k_post.hip", "driver.hip", "capi.hip"]
+SOURCES = ["k_modmm.hip", "k_modmm_i8.hip", "k_batched.hip", "k_trsm.hip", "k_perm.hip", "k_basecase.hip", "k_post.hip", "k_lincomb.hip", "driver.hip", "capi.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-command-line-argument", "-I", INC, "-I", CSRC]

@@ -140,8 +140,8 @@ struct Layout {
     // branch 0 (the caller's) at offset 0; branch b at b * branch_bytes
     size_t stat_off, idx_off, w_off, w2_off, scratch_off, limb_off, branch_bytes;
     int nbranch;
-    size_t tab_off, spec_off, total;
-    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes, limb_bytes, spec_bytes;
+    size_t tab_off, spec_off, wino_off, total;
+    size_t idx_elems, scratch_bytes, tab_bytes, w_bytes, limb_bytes, spec_bytes, wino_bytes;
 };
 
 // Largest matrix (bytes) for which the workspace holds a copy of A, taken
@@ -170,7 +170,17 @@ int branches_for(int64_t m, int64_t n, const pluq_opts *o) {
     return std::min(b, 16);
 }
 
-Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec, int nbranch, bool inplace) {
+// Winograd buffers of the caller's branch: room for the largest update of
+// the recursion (at most ceil(m/2) x ceil(n/2), inner dimension at most the
+// smaller of the two) when it can reach the tuned threshold smin.
+size_t wino_bytes_for(int64_t m, int64_t n, size_t esz, int form, bool inplace, int64_t smin) {
+    if (form == PLUQ_FORM_INT8 || inplace || smin <= 0 || std::min(m, n) < 2 * smin) return 0;
+    const int64_t mh = (m + 1) / 2, nh = (n + 1) / 2;
+    return (size_t)winograd_elems(mh, nh, std::min(mh, nh)) * esz;
+}
+
+Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec, int nbranch, bool inplace,
+              int64_t smin) {
     Layout L;
     L.idx_elems = (size_t)(4 * (m + n) + 65536);
     const size_t full = (size_t)m * (size_t)n * esz;
@@ -195,7 +205,9 @@ Layout layout(int64_t m, int64_t n, size_t esz, uint64_t p, int form, bool spec,
     L.tab_off = (size_t)nbranch * L.branch_bytes;
     L.spec_bytes = (spec && full <= SPEC_MAX_BYTES) ? full : 0;
     L.spec_off = L.tab_off + align_up(L.tab_bytes);
-    L.total = L.spec_off + align_up(L.spec_bytes);
+    L.wino_bytes = wino_bytes_for(m, n, esz, form, inplace, smin);
+    L.wino_off = L.spec_off + align_up(L.spec_bytes);
+    L.total = L.wino_off + align_up(L.wino_bytes);
     return L;
 }
 
@@ -328,6 +340,7 @@ pluq_tune tune_for(int32_t form, uint64_t p, int32_t dtype, int64_t m, int64_t n
     if (t.i8_min_work <= 0) t.i8_min_work = (int64_t)I8_MIN_WORK;
     if (t.batch_panel != 8 && t.batch_panel != 16) t.batch_panel = 8;
     if (t.batch_groups <= 0 || t.batch_groups > 8) t.batch_groups = t.batch_panel == 8 ? 4 : 2;
+    if (t.strassen_min <= 0) t.strassen_min = (int32_t)STRASSEN_MIN;
     return t;
 }
 
@@ -348,9 +361,11 @@ pluq_status modmm_check(int64_t m, int64_t n, int64_t k, const void *dC, int64_t
 
 // C <- C - A B on the caller's stream; `limb` / `limb_bytes` hold the INT8
 // form's digit planes.  noprof: no event timing (nothing is allocated).
+// wino / wino_bytes: when given (FP64 / FP32 forms), one level of
+// Winograd's scheme with these buffers.
 pluq_status modmm_run(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
                       const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form, char *limb,
-                      size_t limb_bytes, bool noprof, void *stream) {
+                      size_t limb_bytes, bool noprof, void *stream, char *wino = nullptr, size_t wino_bytes = 0) {
     MMProblem pb;
     std::memset(&pb, 0, sizeof(pb));
     pb.C = dC;
@@ -380,8 +395,12 @@ pluq_status modmm_run(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, co
             c.limb = limb;
             c.limb_bytes = limb_bytes;
             if (!c.mm_i8(pb)) return PLUQ_ERR_WORKSPACE;
+        } else if (wino) {
+            c.wino = wino;
+            c.wino_bytes = wino_bytes;
+            c.mm_winograd(pb, 0);
         } else {
-            c.mm(&pb, 1);
+            c.mm_launch(&pb, 1);
         }
     } catch (const DeviceError &e) {
         set_err("pluq_modmm: HIP call", e.e);
@@ -439,8 +458,10 @@ const char *pluq_last_error(void) { return g_err; }
 
 size_t pluq_workspace_size(int64_t m, int64_t n, pluq_dtype dt, uint64_t p, const pluq_opts *opts) {
     if (check_common(m, n, std::max<int64_t>(1, n), dt, p, opts) != PLUQ_OK) return 0;
-    return layout(m, n, esize(dt), p, opts ? opts->form : PLUQ_FORM_FP64, !(opts && opts->no_speculation),
-                  branches_for(m, n, opts), in_place(opts)).total;
+    const int form = opts ? opts->form : PLUQ_FORM_FP64;
+    const pluq_tune tp = tune_for(form, p, (int32_t)dt, m, n, nullptr);
+    return layout(m, n, esize(dt), p, form, !(opts && opts->no_speculation), branches_for(m, n, opts),
+                  in_place(opts), tp.strassen_min).total;
 }
 
 pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt, uint64_t p, int64_t *dP,
@@ -454,8 +475,9 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
     const int form = opts ? opts->form : PLUQ_FORM_FP64;
     if ((s = form_check(form, p)) != PLUQ_OK) return s;
     const size_t esz = esize(dt);
+    const pluq_tune tp = tune_for(form, p, (int32_t)dt, m, n, nullptr);
     const Layout L = layout(m, n, esz, p, form, !(opts && opts->no_speculation), branches_for(m, n, opts),
-                            in_place(opts));
+                            in_place(opts), tp.strassen_min);
     if (work_bytes < L.total || (m > 0 && n > 0 && !dWork)) return PLUQ_ERR_WORKSPACE;
     if (dWork && ((uintptr_t)dWork % ALIGN)) return PLUQ_ERR_ARG;
 
@@ -471,7 +493,6 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
         c.kchunk32 = (int)fp32_kchunk(p);
         c.cap = bc_cap();
         if (c.cap <= 0) return PLUQ_ERR_DEVICE;
-        const pluq_tune tp = tune_for(form, p, (int32_t)dt, m, n, nullptr);
         c.mm_t128 = tp.mm_tiles128;
         c.mm_t64 = tp.mm_tiles64;
         c.i8_min_work = (double)tp.i8_min_work;
@@ -486,6 +507,11 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             c.stat_mapped = true;
         }
         c.use_branch(branch_at(w, L, 0));
+        if (L.wino_bytes) {
+            c.wino = w + L.wino_off;
+            c.wino_bytes = L.wino_bytes;
+            c.strassen_min = tp.strassen_min;
+        }
         c.h_idx = g_pin.idx;
         c.h_stat = g_pin.stat;
         // helper branches for PLUQ(F) || PLUQ(G)
@@ -757,6 +783,25 @@ pluq_status pluq_modmm(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, c
     return modmm_run(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form, (char *)dWork, work_bytes, false, stream);
 }
 
+size_t pluq_modmm_winograd_workspace_size(int64_t m, int64_t n, int64_t k, pluq_dtype dt) {
+    if (m < 2 || n < 2 || k < 2 || esize(dt) == 0) return 0;
+    return align_up((size_t)winograd_elems(m, n, k) * esize(dt));
+}
+
+pluq_status pluq_modmm_winograd(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA,
+                                int64_t lda, const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form,
+                                void *dWork, size_t work_bytes, void *stream) {
+    pluq_status s = modmm_check(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form);
+    if (s != PLUQ_OK) return s;
+    if (form == PLUQ_FORM_INT8) return PLUQ_ERR_UNSUPPORTED;
+    if (m < 2 || n < 2 || k < 2) return PLUQ_ERR_ARG;
+    const size_t need = pluq_modmm_winograd_workspace_size(m, n, k, dt);
+    if (!dWork || work_bytes < need) return PLUQ_ERR_WORKSPACE;
+    if ((uintptr_t)dWork % ALIGN) return PLUQ_ERR_ARG;
+    return modmm_run(m, n, k, dC, ldc, dA, lda, dB, ldb, dt, p, form, nullptr, 0, false, stream, (char *)dWork,
+                     work_bytes);
+}
+
 pluq_status pluq_modmm_noalloc(int64_t m, int64_t n, int64_t k, void *dC, int64_t ldc, const void *dA, int64_t lda,
                                const void *dB, int64_t ldb, pluq_dtype dt, uint64_t p, int32_t form,
                                void *stream) {
@@ -1024,7 +1069,7 @@ pluq_status pluq_tune_set(int32_t form, int32_t pclass, int32_t dtype, int32_t b
     if (t->cutoff < 0 || t->cutoff > 128 || (t->cutoff > 0 && t->cutoff < 16) || t->mm_tiles128 < 0 ||
         t->mm_tiles64 < 0 || t->fork_min_dim < 0 || t->i8_min_work < 0 ||
         (t->batch_panel != 0 && t->batch_panel != 8 && t->batch_panel != 16) || t->batch_groups < 0 ||
-        t->batch_groups > 8)
+        t->batch_groups > 8 || t->strassen_min < 0 || (t->strassen_min > 0 && t->strassen_min < 128))
         return PLUQ_ERR_ARG;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     for (TuneEntry &e : g_tune)

@@ -179,6 +179,37 @@ void Ctx::mm(MMProblem *probs, int n) {
     for (int q = 0; q < n; ++q)
         if (probs[q].M > 0 && probs[q].N > 0 && (probs[q].K[0] > 0 || probs[q].K[1] > 0)) probs[live++] = probs[q];
     if (!live) return;
+    if (form != PLUQ_FORM_INT8 && wino && strassen_min > 0) {
+        // Large updates take one level of Winograd's scheme (7 block
+        // products instead of 8), pair by pair; what stays classical runs
+        // afterwards in the grouped launch and then reports non-zero
+        // outputs, else the last Winograd pair does.
+        int rest = 0;
+        for (int q = 0; q < live; ++q) {
+            MMProblem pb = probs[q];
+            bool w[2] = {false, false};
+            for (int s = 0; s < 2; ++s)
+                w[s] = pb.K[s] > 0 && pb.inplace == 0 &&
+                       std::min<int64_t>(std::min(pb.M, pb.N), pb.K[s]) >= strassen_min &&
+                       (size_t)winograd_elems(pb.M, pb.N, pb.K[s]) * esz <= wino_bytes;
+            if (!w[0] && !w[1]) {
+                probs[rest++] = pb;
+                continue;
+            }
+            const bool classical_left = (pb.K[0] > 0 && !w[0]) || (pb.K[1] > 0 && !w[1]);
+            const int last = w[1] ? 1 : 0;
+            for (int s = 0; s < 2; ++s) {
+                if (!w[s]) continue;
+                MMProblem one = pb;
+                if (classical_left || s != last) one.nzflag = nullptr;
+                mm_winograd(one, s);
+                pb.K[s] = 0;
+            }
+            if (classical_left) probs[rest++] = pb;
+        }
+        live = rest;
+        if (!live) return;
+    }
     if (form == PLUQ_FORM_INT8 && limb) {
         // Large updates go to the int8 matrix cores; small ones (latency
         // bound either way) stay in the FP64 kernel, grouped.
@@ -192,6 +223,10 @@ void Ctx::mm(MMProblem *probs, int n) {
         live = rest;
         if (!live) return;
     }
+    mm_launch(probs, live);
+}
+
+void Ctx::mm_launch(MMProblem *probs, int live) {
     double flops = 0, bytes = 0;
     for (int q = 0; q < live; ++q) {
         const double M = probs[q].M, N = probs[q].N;
@@ -315,6 +350,125 @@ static void mmpair(MMProblem &pb, int s, const void *A, int64_t lda, const void 
     pb.B[s] = B;
     pb.ldb[s] = ldb;
     pb.K[s] = (int32_t)K;
+}
+
+// ------------------------------------------------------------- Winograd --
+
+// One level of Winograd's form of Strassen's product for C <- C - A B
+// (pair s): with the 2 x 2 blocks of floor(M/2) x floor(K/2),
+// floor(K/2) x floor(N/2) and floor(M/2) x floor(N/2),
+//   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2,
+//   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21,
+//   M1 = A11 B11, M2 = A12 B21, M3 = S4 B22, M4 = A22 T4,
+//   M5 = S1 T1, M6 = S2 T2, M7 = S3 T3,
+//   C11 -= M1 + M2,            C12 -= M1 + M6 + M5 + M3,
+//   C21 -= M1 + M6 + M7 - M4,  C22 -= M1 + M6 + M7 + M5.
+// Two block products are kept negated (X1 accumulates -(M1 + M6 + M7),
+// X3 = -M5); the sums go to two A-shaped and two B-shaped buffers that are
+// reused as soon as their last product has run, and M4 is added by
+// subtracting A22 (-T4).  Every sum and product is reduced to a canonical
+// residue, so the MM kernel's bounds hold as for the inputs and the result
+// is exactly the classical one.  A last inner index, row or column left by
+// odd sizes is updated classically at the end.
+void Ctx::mm_winograd(const MMProblem &pb, int s) {
+    const int64_t M = pb.M, N = pb.N, K = pb.K[s];
+    const int64_t m2 = M / 2, n2 = N / 2, k2 = K / 2;
+    if (m2 < 1 || n2 < 1 || k2 < 1 || (size_t)winograd_elems(M, N, K) * esz > wino_bytes)
+        throw DeviceError{hipErrorInvalidValue};
+    const int64_t e = (int64_t)esz;
+    const char *A = (const char *)pb.A[s], *B = (const char *)pb.B[s];
+    char *C = (char *)pb.C;
+    const int64_t lda = pb.lda[s], ldb = pb.ldb[s], ldc = pb.ldc;
+    auto cblk = [&](const char *base, int64_t ld, int64_t i, int64_t j) { return base + (i * ld + j) * e; };
+    auto blk = [&](char *base, int64_t ld, int64_t i, int64_t j) { return base + (i * ld + j) * e; };
+    char *Sa = wino, *Sb = Sa + m2 * k2 * e, *Ta = Sb + m2 * k2 * e, *Tb = Ta + k2 * n2 * e;
+    char *X1 = Tb + k2 * n2 * e, *X3 = X1 + m2 * n2 * e;
+    const char *A11 = cblk(A, lda, 0, 0), *A12 = cblk(A, lda, 0, k2), *A21 = cblk(A, lda, m2, 0),
+               *A22 = cblk(A, lda, m2, k2);
+    const char *B11 = cblk(B, ldb, 0, 0), *B12 = cblk(B, ldb, 0, n2), *B21 = cblk(B, ldb, k2, 0),
+               *B22 = cblk(B, ldb, k2, n2);
+    char *C11 = blk(C, ldc, 0, 0), *C12 = blk(C, ldc, 0, n2), *C21 = blk(C, ldc, m2, 0), *C22 = blk(C, ldc, m2, n2);
+    // the final values of the even block come from these writers unless a
+    // last inner index is still to be added
+    int32_t *fin = (K & 1) ? nullptr : pb.nzflag;
+    struct Op {
+        const char *x;
+        int64_t ld;
+        int c;
+    };
+    auto lin = [&](char *out, int64_t ldo, int64_t rows, int64_t cols, Op a, Op b, Op c, int32_t *flag) {
+        LinComb l;
+        l.out = out;
+        l.ldo = ldo;
+        const Op ops[3] = {a, b, c};
+        int nops = 0;
+        for (int t = 0; t < 3; ++t) {
+            l.X[t] = ops[t].x;
+            l.ld[t] = ops[t].ld;
+            l.c[t] = ops[t].c;
+            nops += (ops[t].x && ops[t].c) ? 1 : 0;
+        }
+        l.rows = rows;
+        l.cols = cols;
+        l.nzflag = flag;
+        l.nzgen = pb.nzgen;
+        launch(K_LINCOMB, 0, (double)(nops + 1) * (double)rows * (double)cols * (double)esz,
+               [&] { return launch_lincomb(dt, l, (double)p, st); });
+    };
+    const Op none{nullptr, 0, 0};
+    auto prod = [&](char *Cb, int64_t ldcb, const char *Ab, int64_t ldab, const char *Bb, int64_t ldbb, int32_t *flag) {
+        MMProblem q = mmprob(Cb, ldcb, m2, n2);
+        mmpair(q, 0, Ab, ldab, Bb, ldbb, k2);
+        q.nzflag = flag;
+        q.nzgen = pb.nzgen;
+        mm_launch(&q, 1);
+    };
+    lin(X1, n2, m2, n2, none, none, none, nullptr);                                  // X1 = 0
+    prod(X1, n2, A11, lda, B11, ldb, nullptr);                                       // X1 = -M1
+    lin(C11, ldc, m2, n2, {C11, ldc, 1}, {X1, n2, 1}, none, nullptr);                // C11 -= M1
+    prod(C11, ldc, A12, lda, B21, ldb, fin);                                         // C11 -= M2
+    lin(Sa, k2, m2, k2, {A21, lda, 1}, {A22, lda, 1}, none, nullptr);                // S1
+    lin(Ta, n2, k2, n2, {B12, ldb, 1}, {B11, ldb, -1}, none, nullptr);               // T1
+    lin(X3, n2, m2, n2, none, none, none, nullptr);
+    prod(X3, n2, Sa, k2, Ta, n2, nullptr);                                           // X3 = -M5
+    lin(Sb, k2, m2, k2, {Sa, k2, 1}, {A11, lda, -1}, none, nullptr);                 // S2
+    lin(Tb, n2, k2, n2, {B22, ldb, 1}, {Ta, n2, -1}, none, nullptr);                 // T2
+    prod(X1, n2, Sb, k2, Tb, n2, nullptr);                                           // X1 = -(M1 + M6)
+    lin(Sa, k2, m2, k2, {A12, lda, 1}, {Sb, k2, -1}, none, nullptr);                 // S4
+    lin(C12, ldc, m2, n2, {C12, ldc, 1}, {X1, n2, 1}, {X3, n2, 1}, nullptr);         // C12 -= M1 + M6 + M5
+    prod(C12, ldc, Sa, k2, B22, ldb, fin);                                           // C12 -= M3
+    lin(Sa, k2, m2, k2, {A11, lda, 1}, {A21, lda, -1}, none, nullptr);               // S3
+    lin(Ta, n2, k2, n2, {B22, ldb, 1}, {B12, ldb, -1}, none, nullptr);               // T3
+    prod(X1, n2, Sa, k2, Ta, n2, nullptr);                                           // X1 = -(M1 + M6 + M7)
+    lin(C22, ldc, m2, n2, {C22, ldc, 1}, {X1, n2, 1}, {X3, n2, 1}, fin);             // C22 -= M1 + M6 + M7 + M5
+    lin(Ta, n2, k2, n2, {B21, ldb, 1}, {Tb, n2, -1}, none, nullptr);                 // -T4
+    lin(C21, ldc, m2, n2, {C21, ldc, 1}, {X1, n2, 1}, none, nullptr);                // C21 -= M1 + M6 + M7
+    prod(C21, ldc, A22, lda, Ta, n2, fin);                                           // C21 += M4
+    // leftovers of odd sizes (disjoint parts of C, one grouped launch): the
+    // last inner index over the even block, the last row and the last
+    // column over the whole inner dimension
+    MMProblem rest[3];
+    int nr = 0;
+    if (K & 1) {
+        rest[nr] = mmprob(C, ldc, 2 * m2, 2 * n2);
+        mmpair(rest[nr], 0, cblk(A, lda, 0, 2 * k2), lda, cblk(B, ldb, 2 * k2, 0), ldb, 1);
+        ++nr;
+    }
+    if (M & 1) {
+        rest[nr] = mmprob(blk(C, ldc, 2 * m2, 0), ldc, 1, N);
+        mmpair(rest[nr], 0, cblk(A, lda, 2 * m2, 0), lda, B, ldb, K);
+        ++nr;
+    }
+    if (N & 1) {
+        rest[nr] = mmprob(blk(C, ldc, 0, 2 * n2), ldc, 2 * m2, 1);
+        mmpair(rest[nr], 0, A, lda, cblk(B, ldb, 0, 2 * n2), ldb, K);
+        ++nr;
+    }
+    for (int q = 0; q < nr; ++q) {
+        rest[q].nzflag = pb.nzflag;
+        rest[q].nzgen = pb.nzgen;
+    }
+    if (nr) mm_launch(rest, nr);
 }
 
 // ------------------------------------------------------------------ TRSM --
@@ -827,6 +981,8 @@ void Ctx::use_branch(const Branch &b) {
     trsm_w2 = b.trsm_w2;
     limb = b.limb;
     limb_bytes = b.limb_bytes;
+    wino = nullptr;   // the Winograd buffers belong to the caller's branch
+    wino_bytes = 0;
     if (!stat_mapped) d_stat = b.d_stat;
 }
 

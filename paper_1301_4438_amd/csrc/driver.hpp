@@ -28,10 +28,10 @@ struct Stats {
 extern thread_local Stats g_last_stats;
 
 // Per-kernel-class device timing (HIP events), per host thread.
-constexpr int KCLASSES = 9;
+constexpr int KCLASSES = 10;
 enum KClass {
     K_MODMM = 0, K_TRSM = 1, K_PERM = 2, K_BASE = 3, K_SCAN = 4, K_LIMB = 5, K_MODMM_I8 = 6, K_TRSM_DIAG = 7,
-    K_BASE_RPM = 8
+    K_BASE_RPM = 8, K_LINCOMB = 9
 };
 struct KStat {
     int64_t launches = 0;
@@ -58,6 +58,16 @@ extern thread_local Profiler g_prof;
 // INT8-limb form: updates with fewer multiply-adds than this stay in the FP64
 // kernel (a split launch costs more than it saves on small updates).
 constexpr double I8_MIN_WORK = 64.0 * 1024 * 1024;
+
+// FP64 / FP32 forms: MM updates whose three dimensions are all at least this
+// take one level of Winograd's 7-product scheme (default; tuned).
+constexpr int64_t STRASSEN_MIN = 4096;
+// Elements of the Winograd buffers for one M x N x K product: two block sums
+// of each operand and two block products.
+inline int64_t winograd_elems(int64_t M, int64_t N, int64_t K) {
+    const int64_t m2 = M / 2, n2 = N / 2, k2 = K / 2;
+    return 2 * (m2 * k2 + k2 * n2 + m2 * n2);
+}
 
 enum Zero { Z_UNKNOWN = 0, Z_ZERO = 1, Z_NONZERO = 2 };
 
@@ -141,6 +151,9 @@ struct Ctx {
     char *trsm_w2 = nullptr;         // the same for the upper solve of a node's pair
     char *limb = nullptr;            // digit planes of the INT8-limb form (or null)
     size_t limb_bytes = 0;
+    char *wino = nullptr;            // Winograd block sums and products (or null)
+    size_t wino_bytes = 0;
+    int64_t strassen_min = STRASSEN_MIN;
     int kchunk32 = 0;                // FP32 form: products between reductions
     // tuned parameters (performance only)
     int mm_t128 = 240, mm_t64 = 192;    // MM tile choice thresholds
@@ -184,7 +197,11 @@ struct Ctx {
     void perm_rows(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
     void perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
     void mm(MMProblem *probs, int n);
+    void mm_launch(MMProblem *probs, int n);   // the classical kernel of the form, no splitting
     bool mm_i8(const MMProblem &pb);
+    // C (M x N) <- C - A B by one level of Winograd's scheme (pair s of pb);
+    // nzflag / nzgen of pb are set by the writers of C's final values.
+    void mm_winograd(const MMProblem &pb, int s);
     void trsm_pair(int64_t ti, int64_t tj, int64_t r, int64_t di, int64_t dj, int64_t ncols, int64_t ei, int64_t ej,
                    int64_t nrows);
     void trsm_pair_rec(const char *T, int64_t r, char *BD, char *BE, int64_t ncols, int64_t nrows, int64_t off);

@@ -151,6 +151,23 @@ hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, do
 int bc_capacity();        // maximum rows (and columns) of a base-case tile
 hipError_t bc_init();     // one-time set-up of the base-case kernels
 
+// ---- Winograd's block sums and combinations (k_lincomb.hip) ----
+// out (rows x cols, ldo) <- (c[0] X[0] + c[1] X[1] + c[2] X[2]) mod p,
+// canonical; c[t] in {-1, 0, 1}, a null X[t] or zero c[t] is left out (all
+// three left out: out <- 0).  out may be one of the X[t].  nzflag as in
+// MMProblem.
+struct LinComb {
+    void *out;
+    int64_t ldo;
+    const void *X[3];
+    int64_t ld[3];
+    int32_t c[3];
+    int64_t rows, cols;
+    int32_t *nzflag;
+    int32_t nzgen;
+};
+hipError_t launch_lincomb(int dtype, const LinComb &a, double p, hipStream_t st);
+
 // ---- outputs derived by permutation (k_post.hip) ----
 hipError_t launch_fill_i32(int32_t *x, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_inverse_map(const int64_t *P, int64_t n, int32_t *inv, hipStream_t st);

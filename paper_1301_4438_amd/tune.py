@@ -12,6 +12,8 @@ parameter at a time (coordinate descent from the built-in defaults):
   mm_tiles128   MM launches take 128 x 128 tiles from this many tiles on;
   mm_tiles64    ... 64 x 64 tiles from this many on, else 32 x 32;
   i8_min_work   INT8 form: smaller updates stay in the FP64 kernel;
+  strassen_min  FP64 / FP32 forms: updates whose three dimensions reach it
+                take one level of Winograd's 7-product scheme;
 
 and, for the batched form (key form 3), the panel width and the persistent
 work-groups per compute unit on a batch of the 4096-matrix workload's
@@ -91,6 +93,9 @@ def tune_decomposition(pl, form, p, n, reps, log):
     space = [("cutoff", [64, 96, 128]), ("mm_tiles128", [120, 240, 480]), ("mm_tiles64", [96, 192, 384])]
     if form == "int8":
         space.append(("i8_min_work", [1 << 24, 1 << 25, 1 << 26, 1 << 27]))
+    elif n >= 4096:
+        # one Winograd level on the updates whose dimensions reach this
+        space.append(("strassen_min", [2048, 4096, 1 << 30]))
     params = {}
     pl.tune_set(*key, **params)
     t_def, d_def = _time_decomp(pl, mats, p, form, reps)

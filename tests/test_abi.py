@@ -169,3 +169,41 @@ def test_tune_cache_well_formed():
     finally:
         pl.tune_clear()
         pl.load_tune_cache()
+
+
+def test_winograd_entry_host_checks():
+    """Argument checks of the Winograd MM entry point, taken before any
+    device work (the pointers are never dereferenced)."""
+    L = pl.load()
+    fake = ctypes.c_void_p(4096)
+    assert L.pluq_modmm_winograd_workspace_size(1, 8, 8, 1) == 0
+    need = L.pluq_modmm_winograd_workspace_size(9, 11, 13, 1)
+    assert need >= 8 * 2 * (4 * 6 + 6 * 5 + 4 * 5)
+    assert L.pluq_modmm_winograd_workspace_size(9, 11, 13, 2) < need
+    args = lambda m, n, k, form, wbytes: (m, n, k, fake, n, fake, k, fake, n, 1, 65521, form, fake, wbytes, None)
+    assert L.pluq_modmm_winograd(*args(9, 11, 13, 1, need)) == pl.PLUQ_ERR_UNSUPPORTED   # INT8 form
+    assert L.pluq_modmm_winograd(*args(1, 11, 13, 0, need)) == pl.PLUQ_ERR_ARG
+    assert L.pluq_modmm_winograd(*args(9, 11, 13, 0, need - 8)) == pl.PLUQ_ERR_WORKSPACE
+
+
+def test_winograd_workspace_follows_threshold():
+    """The decomposition's workspace holds the Winograd buffers only for the
+    FP64 / FP32 forms, outside the in-place variant, and when the matrix can
+    reach the tuned threshold."""
+    pl.tune_clear()
+    try:
+        base = pl.pluq_workspace_size(1024, 1024, 1, 65521, pl._opts("fp64"))
+        pl.tune_set(-1, -1, -1, -1, strassen_min=128)
+        low = pl.pluq_workspace_size(1024, 1024, 1, 65521, pl._opts("fp64"))
+        assert low - base >= 8 * 2 * 3 * 256 * 256
+        assert pl.pluq_workspace_size(1024, 1024, 1, 65521, pl._opts("int8")) == \
+            pl.pluq_workspace_size(1024, 1024, 1, 65521, pl._opts("int8")) and \
+            pl.pluq_workspace_size(1024, 1024, 1, 65521, pl._opts("fp64", in_place=True)) < base
+        pl.tune_clear()
+        pl.tune_set(-1, -1, -1, -1, strassen_min=1 << 30)
+        assert pl.pluq_workspace_size(1024, 1024, 1, 65521, pl._opts("fp64")) == base
+        with pytest.raises(pl.PluqError):
+            pl.tune_set(-1, -1, -1, -1, strassen_min=64)
+    finally:
+        pl.tune_clear()
+        pl.load_tune_cache()
