@@ -26,11 +26,17 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 
 
 def lib():
+    """The oracle's C library (rebuilt when older than its source).
+    PLUQ_ORACLE_LIB names another build of the same source to load instead
+    (the sanitizer build)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC):
-            _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        path = os.environ.get("PLUQ_ORACLE_LIB")
+        if not path:
+            path = _build.LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+                _build.build()
+        L = ctypes.CDLL(path)
         u64, i64 = ctypes.c_uint64, ctypes.c_int64
         L.oracle_inv.restype = u64
         L.oracle_inv.argtypes = [u64, u64]
