@@ -18,12 +18,22 @@
 //   limb_split_kernel -- writes the digit planes of the operand blocks into
 //     workspace, [rows][Kp] int8 with the inner dimension contiguous (B is
 //     transposed on the way through LDS), zero-padded to a multiple of 64.
-//   modmm_i8_kernel   -- 128 x 128 output tile per 256-thread work-group,
-//     2 x 2 waves of 64 x 64, each 2 x 2 blocks of v_mfma_i32_32x32x32_i8;
-//     the planes are staged in LDS 64 bytes of K at a time (rows padded to
-//     80 bytes so that the 16-byte fragment reads of a wave hit distinct
-//     banks) and the next panel's global loads are in flight during the
-//     current panel's matrix-core work.
+//   modmm_i8_kernel   -- 128 x 128 output tile per work-group: for two
+//     digits 2 x 4 waves of 64 x 32 (2 x 1 blocks of v_mfma_i32_32x32x32_i8
+//     per limb product), for one digit 2 x 2 waves of 64 x 64; the planes are staged in LDS 64 bytes of K at a
+//     time (rows padded to 80 bytes so that the 16-byte fragment reads of a
+//     wave hit distinct banks), double-buffered: the next panel's global
+//     loads are issued before the current panel's matrix-core work and
+//     stored into the other buffer after it, so one barrier per panel
+//     suffices.  With the three limb sums of two digits a 64 x 64 wave tile
+//     would fill the AGPRs and leave one wave per SIMD; at 64 x 32 two
+//     waves share each SIMD and cover each other's load and barrier waits.
+//     One digit has a quarter of the matrix-core work per panel and keeps
+//     the larger wave tile for its operand reuse.  Tiles are
+//     handed out XCD by XCD: the work-groups that one XCD runs (hardware
+//     dispatch is round-robin over the 8 XCDs) take a contiguous range of
+//     tiles in an order grouped by 8 tile rows, so that the A and B panels
+//     they share stay in that XCD's L2.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -31,6 +41,11 @@ namespace pluq {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int I8_GROUP = 8;   // tile rows per group of the tile order
+// threads per 128 x 128 tile: 8 waves of 64 x 32 for two digits, 4 waves
+// of 64 x 64 for one
+__host__ __device__ constexpr int i8_threads(int nl) { return nl == 2 ? 512 : 256; }
 
 // ------------------------------------------------------------------ split --
 
@@ -174,77 +189,111 @@ struct I8Args {
 };
 
 template <typename T, int NL>
-__global__ __launch_bounds__(256) void modmm_i8_kernel(const I8Args g) {
+__global__ __launch_bounds__(i8_threads(NL), 2) void modmm_i8_kernel(const I8Args g) {
     constexpr int BM = 128, BN = 128, BK = 64, LDP = BK + 16;
     constexpr int NS = NL == 2 ? 3 : 1;   // limb sums S0 (, S1, S2)
-    __shared__ __attribute__((aligned(16))) int8_t As[NL][BM * LDP];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[NL][BN * LDP];
+    constexpr int JB = NL == 2 ? 1 : 2;   // 32-column blocks per wave
+    constexpr int NT = i8_threads(NL), WN = 4 / JB, RPT = BM / (NT / 4);
+    // two digits: double-buffered panels; one digit: a single buffer (two
+    // barriers per panel), which keeps two work-groups per compute unit
+    constexpr bool DB = NL == 2;
+    constexpr int NB = DB ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) int8_t As[NB][NL][BM * LDP];
+    __shared__ __attribute__((aligned(16))) int8_t Bs[NB][NL][BN * LDP];
 
-    const int tile = blockIdx.x;
-    const int row0 = (tile / g.tilesN) * BM, col0 = (tile % g.tilesN) * BN;
+    // work-group -> tile: XCD x = blockIdx % 8 runs a contiguous range of
+    // the tile order, which walks groups of I8_GROUP tile rows column by
+    // column (a bijection onto [0, tiles) for any count)
+    const int tiles = (int)gridDim.x, tilesN = g.tilesN, tilesM = tiles / tilesN;
+    const int xcd = (int)blockIdx.x % 8, q = (int)blockIdx.x / 8;
+    const int per = tiles / 8, rem = tiles % 8;
+    const int t = xcd * per + min(xcd, rem) + q;
+    const int gsz = I8_GROUP * tilesN, grp = t / gsz;
+    const int gr0 = grp * I8_GROUP, grows = min(tilesM - gr0, I8_GROUP);
+    const int tr = gr0 + (t - grp * gsz) % grows, tc = (t - grp * gsz) / grows;
+    const int row0 = tr * BM, col0 = tc * BN;
     const int M = g.M, N = g.N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave >> 1) * 64, wn0 = (wave & 1) * 64;
+    const int wm0 = (wave / WN) * 64, wn0 = (wave % WN) * 32 * JB;
 
-    v16i acc[NS][2][2];
+    v16i acc[NS][2][JB];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < JB; ++j)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[s][i][j][v] = 0;
 
-    // Global loads: 16 bytes per thread, plane row tid/4 (+64), chunk tid%4.
-    // Rows past M (N) are clamped to the last valid row: their products only
-    // reach outputs that are never stored.
+    // Global loads: 16 bytes per thread, plane and row, plane rows
+    // tid/4 + r NT/4 (r < RPT), chunk tid%4.  Rows past M (N) are clamped
+    // to the last valid row: their products only reach outputs that are
+    // never stored.
     const int lr = tid >> 2, lc = (tid & 3) * 16;
-    const int64_t ar0 = (int64_t)min(row0 + lr, M - 1) * g.lda + lc;
-    const int64_t ar1 = (int64_t)min(row0 + lr + 64, M - 1) * g.lda + lc;
-    const int64_t br0 = (int64_t)min(col0 + lr, N - 1) * g.ldb + lc;
-    const int64_t br1 = (int64_t)min(col0 + lr + 64, N - 1) * g.ldb + lc;
-    v4i pa[NL][2], pb[NL][2];
+    int64_t ar[RPT], br[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        ar[r] = (int64_t)min(row0 + lr + r * (NT / 4), M - 1) * g.lda + lc;
+        br[r] = (int64_t)min(col0 + lr + r * (NT / 4), N - 1) * g.ldb + lc;
+    }
+    v4i pa[NL][RPT], pb[NL][RPT];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            pa[l][0] = *(const v4i *)(g.a[l] + ar0 + k0);
-            pa[l][1] = *(const v4i *)(g.a[l] + ar1 + k0);
-            pb[l][0] = *(const v4i *)(g.b[l] + br0 + k0);
-            pb[l][1] = *(const v4i *)(g.b[l] + br1 + k0);
-        }
+        for (int l = 0; l < NL; ++l)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                pa[l][r] = *(const v4i *)(g.a[l] + ar[r] + k0);
+                pb[l][r] = *(const v4i *)(g.b[l] + br[r] + k0);
+            }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                *(v4i *)&As[buf][l][(lr + r * (NT / 4)) * LDP + lc] = pa[l][r];
+                *(v4i *)&Bs[buf][l][(lr + r * (NT / 4)) * LDP + lc] = pb[l][r];
+            }
     };
 
     const int steps = g.Kp / BK;
-    if (steps > 0) load(0);
+    if (DB && steps > 0) {
+        load(0);
+        stash(0);
+    }
+    if (!DB && steps > 0) load(0);
+    if (DB) __syncthreads();
     for (int s = 0; s < steps; ++s) {
-        __syncthreads();
-#pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            *(v4i *)&As[l][lr * LDP + lc] = pa[l][0];
-            *(v4i *)&As[l][(lr + 64) * LDP + lc] = pa[l][1];
-            *(v4i *)&Bs[l][lr * LDP + lc] = pb[l][0];
-            *(v4i *)&Bs[l][(lr + 64) * LDP + lc] = pb[l][1];
+        const int buf = DB ? (s & 1) : 0;
+        if (!DB) {
+            __syncthreads();
+            stash(0);
+            __syncthreads();
         }
-        __syncthreads();
+        // next panel in flight during this one's products; with two
+        // buffers it is stored into the other one, which every wave
+        // finished reading before the barrier that ended the previous step
         if (s + 1 < steps) load((s + 1) * BK);
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             // v_mfma_i32_32x32x32_i8: lane holds row (A) / column (B) lane%32
             // and inner indices 16*(lane/32) .. +15 of the 32-deep step.
             const int ko = ks * 32 + (lane >> 5) * 16;
-            v4i fa[NL][2], fb[NL][2];
+            v4i fa[NL][2], fb[NL][JB];
 #pragma unroll
-            for (int l = 0; l < NL; ++l)
+            for (int l = 0; l < NL; ++l) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    fa[l][i] = *(const v4i *)&As[l][(wm0 + 32 * i + (lane & 31)) * LDP + ko];
-                    fb[l][i] = *(const v4i *)&Bs[l][(wn0 + 32 * i + (lane & 31)) * LDP + ko];
-                }
+                for (int i = 0; i < 2; ++i)
+                    fa[l][i] = *(const v4i *)&As[buf][l][(wm0 + 32 * i + (lane & 31)) * LDP + ko];
+#pragma unroll
+                for (int j = 0; j < JB; ++j)
+                    fb[l][j] = *(const v4i *)&Bs[buf][l][(wn0 + 32 * j + (lane & 31)) * LDP + ko];
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
+                for (int j = 0; j < JB; ++j) {
                     acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[0][j], acc[0][i][j], 0, 0, 0);
                     if (NL == 2) {
                         acc[NS - 2][i][j] =
@@ -256,17 +305,23 @@ __global__ __launch_bounds__(256) void modmm_i8_kernel(const I8Args g) {
                     }
                 }
         }
+        if (DB) {
+            if (s + 1 < steps) stash(buf ^ 1);
+            __syncthreads();
+        }
     }
 
     // Epilogue: element v of a 32 x 32 block sits at row
-    // 8*(v/4) + 4*(lane/32) + v%4 and column lane%32.
+    // 8*(v/4) + 4*(lane/32) + v%4 and column lane%32.  A block's 16 C
+    // entries are loaded before any is used (clamped addresses), so those
+    // loads are in flight together.
     const ModP mod = g.mod;
     T *C = (T *)g.C;
     bool nz = false;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int i = 0; i < 2; ++i) {
             const int gc = col0 + wn0 + 32 * j + (lane & 31);
             double cv[16];
 #pragma unroll
@@ -291,7 +346,7 @@ __global__ __launch_bounds__(256) void modmm_i8_kernel(const I8Args g) {
 
 template <typename T, int NL>
 static hipError_t i8_t(I8Args &a, int total, hipStream_t st) {
-    PLUQ_LAUNCH((modmm_i8_kernel<T, NL>), dim3(total), dim3(256), 0, st, a);
+    PLUQ_LAUNCH((modmm_i8_kernel<T, NL>), dim3(total), dim3(i8_threads(NL)), 0, st, a);
     return hipGetLastError();
 }
 
