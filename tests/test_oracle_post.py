@@ -117,3 +117,19 @@ def test_leu_pins_bite():
         mistakes["ubar_side"] |= not passes(A, p, Lb, E, Qm @ Uraw @ Qm.T)
         mistakes["no_identity"] |= m > r and not passes(A, p, Pm @ Lcut @ Pm.T, E, Ub)
     assert all(mistakes.values()), mistakes
+
+
+def test_echelon_cofactor_not_echelon_in_general():
+    """The co-factor of the column echelon form is not itself in echelon
+    form in general: Algorithm 1 pairs the ascending pivot rows with columns
+    that are not ascending, in the order of its recursion (this is why the
+    triangular factor of a CUP decomposition is not reachable by permutation
+    alone).  Some input among the cases shows it."""
+    seen = False
+    for A, p in _cases():
+        P, Q, r, X = oracle.pluqz(A, p)
+        _, E, _ = oracle.leu(P, Q, r, X)
+        rows = np.sort(np.asarray(P[:r], np.int64))
+        cols = [int(np.nonzero(E[i])[0][0]) for i in rows]
+        seen |= any(b < a for a, b in zip(cols, cols[1:]))
+    assert seen
