@@ -519,22 +519,29 @@ __global__ __launch_bounds__(TILE * 4) void bc_lu_kernel(T *A, int64_t lda, int 
 // Rank profile matrix of the tile: status[0] = r, status[1 + i] = pivot
 // column of row i or -1.  Rows are processed in order; the pivot of row i is
 // the first non-zero entry of the reduced row among the columns that are not
-// yet pivot columns.  (Taken for non-generic tiles only.)  Same register
-// layout as the elimination kernel with 256 threads (R x R entries per
-// thread); rows run in blocks of 16 so that the row owners' register row is
-// a compile-time index; each thread keeps the pivot columns among its own
-// columns as a bit mask; the pivot inverse comes from the LDS table when p
-// <= 65536; the tile is reduced (symmetric reduction) after every block of 16
-// rows, or after every pivot when RED1 (p close to 2^25).
+// yet pivot columns.  (Taken for non-generic tiles only.)  256 threads,
+// thread (ty, tx) = (tid / 16, tid % 16) holding entries (ty + 16 a,
+// tx + 16 b) in registers; rows run in blocks of 16 so that the row owners'
+// register row is a compile-time index; each thread keeps the pivot columns
+// among its own columns as a bit mask.  One barrier per row: the owners of
+// row i reduce it and publish it (pivot and dead columns as 0) with their
+// first non-zero column; after the barrier every thread finds the pivot
+// column, reads the pivot and its inverse (LDS table when p <= 65536) itself,
+// fetches column jc of its own rows from the lane of its 16-lane group that
+// holds it (a within-wave shuffle), forms its multipliers, and applies the
+// row to its 8 x 8 entries with branch-free multiply-adds (multipliers of
+// rows <= i and published values of dead columns are 0).  Row i's values and
+// first-column words are double-buffered by row parity, so the next row's
+// owners can publish while the others still read.  The tile is reduced
+// (symmetric reduction) after every block of 16 rows, or after every pivot
+// when RED1 (p close to 2^25).
 template <typename T, bool RED1>
 __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t lda, int m, int n, ModP mod,
                                                             const uint16_t *gtab, int32_t *status) {
     constexpr int R = 8;
     extern __shared__ __align__(16) unsigned char dyn[];
-    __shared__ double Lb[BC_DIM];
     __shared__ double Ub[2][BC_DIM];
     __shared__ int mins[2][16];
-    __shared__ double s_inv;
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
     const uint16_t *tab = nullptr;
@@ -578,6 +585,8 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
 #pragma unroll
             for (int b = 0; b < R; ++b) v[a][b] = sym_reduce(v[a][b], mod);
     };
+    // the first lane of this thread's 16-lane group (same ty) within the wave
+    const int grp = tid & 48;
     auto row_step = [&](int i, auto AI) __attribute__((always_inline)) {
         constexpr int ai = decltype(AI)::value;
         const int buf = i & 1;
@@ -586,12 +595,11 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
 #pragma unroll
             for (int b = 0; b < R; ++b) {
                 const int j = tx + 16 * b;
-                if (j < n && !((dead >> b) & 1u)) {
-                    const double u = sym_reduce(v[ai][b], mod);
-                    v[ai][b] = u;
-                    Ub[buf][j] = u;
-                    if (u != 0.0 && j < first) first = j;
-                }
+                const bool live = j < n && !((dead >> b) & 1u);
+                const double u = live ? sym_reduce(v[ai][b], mod) : 0.0;
+                if (live) v[ai][b] = u;
+                Ub[buf][j] = u;
+                if (u != 0.0 && j < first) first = j;
             }
             mins[buf][tx] = first;
         }
@@ -601,50 +609,35 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
         for (int t = 0; t < 16; ++t) jc = min(jc, mins[buf][t]);
         if (jc >= n) return;   // dependent row (uniform)
         ++r;
-        const int bj = jc >> 4;
-        if (ty == (i & 15) && tx == (jc & 15)) {
-            double pv = 0.0;
-#pragma unroll
-            for (int b = 0; b < R; ++b)
-                if (b == bj) pv = v[ai][b];
-            if (pv < 0.0) pv += mod.p;   // canonical, for the inverse
-            s_inv = tab ? (double)tab[(int)pv] : mod_inv(pv, mod);
-            status[1 + i] = jc;
-        }
-        if (tx == (jc & 15)) dead |= 1u << bj;
-        __syncthreads();
-        const double inv = s_inv;
-        if (tx == (jc & 15)) {
-#pragma unroll
-            for (int a = 0; a < R; ++a) {
-                const int k = ty + 16 * a;
-                if (k > i && k < m) {
-                    double c = 0.0;
-#pragma unroll
-                    for (int b = 0; b < R; ++b)
-                        if (b == bj) c = v[a][b];
-                    Lb[k] = sym_reduce(sym_reduce(c, mod) * inv, mod);
-                }
-            }
-        }
-        __syncthreads();
+        const int bj = jc >> 4, sl = jc & 15;
+        double pv = Ub[buf][jc];
+        if (pv < 0.0) pv += mod.p;   // canonical, for the inverse
+        const double inv = tab ? (double)tab[(int)pv] : mod_inv(pv, mod);
+        if (tid == 0) status[1 + i] = jc;
+        if (tx == sl) dead |= 1u << bj;
+        // multipliers: column jc of rows ty + 16 a sits in lane grp + sl,
+        // register v[a][bj]
+        double l[R];
 #pragma unroll
         for (int a = 0; a < R; ++a) {
-            const int k = ty + 16 * a;
-            if (k > i && k < m) {
-                const double l = Lb[k];
+            double sel = 0.0;
 #pragma unroll
-                for (int b = 0; b < R; ++b) {
-                    const int j = tx + 16 * b;
-                    if (j < n && !((dead >> b) & 1u)) v[a][b] = fma(-l, Ub[buf][j], v[a][b]);
-                }
-            }
+            for (int b = 0; b < R; ++b) sel = (b == bj) ? v[a][b] : sel;
+            const double c = __shfl(sel, grp + sl, 64);
+            const int k = ty + 16 * a;
+            l[a] = (k > i && k < m) ? sym_reduce(sym_reduce(c, mod) * inv, mod) : 0.0;
         }
+        double u[R];
+#pragma unroll
+        for (int b = 0; b < R; ++b) u[b] = Ub[buf][tx + 16 * b];
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
         if (RED1) reduce_all();
-        // Ub and mins are double-buffered: the next row's owners fill the
-        // other half before its first barrier.  Lb and s_inv are rewritten
-        // only after that barrier, which every thread reaches after this
-        // update.
+        // Ub and mins of this row are read again only by threads that have
+        // not yet passed the next row's barrier; the row after next rewrites
+        // them after that barrier.
     };
 #define PLUQ_RPM_BLOCK(K)                                                                         \
     {                                                                                             \
