@@ -172,6 +172,68 @@ void Ctx::perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::v
     }
 }
 
+void Ctx::perm_batch(PermJob *jobs, int nj) {
+    struct Live {
+        PermJob j;
+        bool rows, cols;
+        size_t bytes;
+    };
+    std::vector<Live> live;
+    live.reserve((size_t)nj);
+    for (int q = 0; q < nj; ++q) {
+        const PermJob &J = jobs[q];
+        const bool r = J.rmap && J.nr > 1 && J.nc > 0 && !is_identity(*J.rmap);
+        const bool c = J.cmap && J.nc > 1 && J.nr > 0 && !is_identity(*J.cmap);
+        if (!r && !c) continue;
+        if ((r && (int64_t)J.rmap->size() != J.nr) || (c && (int64_t)J.cmap->size() != J.nc))
+            throw DeviceError{hipErrorInvalidValue};
+        if (r) require_permutation(*J.rmap);
+        if (c) require_permutation(*J.cmap);
+        const size_t bytes = ((size_t)J.nr * (size_t)J.nc * esz + 255) & ~(size_t)255;
+        if (bytes > scratch_bytes) {
+            // larger than the scratch: strip-mined, one map at a time
+            if (r) perm_rows(J.gi, J.gj, J.nr, J.nc, *J.rmap);
+            if (c) perm_cols(J.gi, J.gj, J.nr, J.nc, *J.cmap);
+            continue;
+        }
+        live.push_back(Live{J, r, c, bytes});
+    }
+    std::vector<int32_t> maps;
+    size_t q0 = 0;
+    while (q0 < live.size()) {
+        size_t q1 = q0, used = 0;
+        while (q1 < live.size() && q1 - q0 < (size_t)GATHER_MAX_JOBS && used + live[q1].bytes <= scratch_bytes)
+            used += live[q1++].bytes;
+        // the group's maps in one upload
+        maps.clear();
+        size_t off[GATHER_MAX_JOBS][2];
+        for (size_t q = q0; q < q1; ++q) {
+            const Live &L = live[q];
+            off[q - q0][0] = maps.size();
+            if (L.rows) maps.insert(maps.end(), L.j.rmap->begin(), L.j.rmap->end());
+            off[q - q0][1] = maps.size();
+            if (L.cols) maps.insert(maps.end(), L.j.cmap->begin(), L.j.cmap->end());
+        }
+        const int32_t *dmap = upload(maps.data(), (int64_t)maps.size());
+        GatherJob to[GATHER_MAX_JOBS], back[GATHER_MAX_JOBS];
+        char *sp = scratch;
+        double bytes = 0;
+        for (size_t q = q0; q < q1; ++q) {
+            const Live &L = live[q];
+            const int t = (int)(q - q0);
+            to[t] = GatherJob{at(L.j.gi, L.j.gj), lda, sp, L.j.nc, L.j.nr, L.j.nc,
+                              L.rows ? dmap + off[t][0] : nullptr, L.cols ? dmap + off[t][1] : nullptr, 0, 0, 0};
+            back[t] = GatherJob{sp, L.j.nc, at(L.j.gi, L.j.gj), lda, L.j.nr, L.j.nc, nullptr, nullptr, 0, 0, 0};
+            sp += L.bytes;
+            bytes += 2.0 * (double)L.j.nr * (double)L.j.nc * (double)esz;
+        }
+        const int n = (int)(q1 - q0);
+        launch(K_PERM, 0, bytes, [&] { return launch_gather_jobs(dt, to, n, st); });
+        launch(K_PERM, 0, bytes, [&] { return launch_gather_jobs(dt, back, n, st); });
+        q0 = q1;
+    }
+}
+
 // -------------------------------------------------------------------- MM --
 
 void Ctx::mm(MMProblem *probs, int n) {
@@ -784,8 +846,11 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
     // (a speculative attempt does not test the leading quadrant for zero: a
     // generic rank profile has none, and a zero quadrant fails its tiles)
     const int64_t r1 = node(gi, gj, k, h, spec ? Z_NONZERO : Z_UNKNOWN, P1, Q1);
-    perm_rows(gi, gj + h, k, n - h, P1);   // [B1; B2] <- P1^T A2
-    perm_cols(gi + k, gj, m - k, h, Q1);   // [C1 C2] <- A3 Q1^T
+    {
+        PermJob pj[2] = {{gi, gj + h, k, n - h, &P1, nullptr},    // [B1; B2] <- P1^T A2
+                         {gi + k, gj, m - k, h, nullptr, &Q1}};   // [C1 C2] <- A3 Q1^T
+        perm_batch(pj, 2);
+    }
 
     // F = B2 - M1 D, G = C2 - E V1, H = A4 - E D
     Blk bF{gi + r1, gj + h, k - r1, n - h}, bG{gi + k, gj + r1, m - k, h - r1}, bH{gi + k, gj + h, m - k, n - h};
@@ -828,13 +893,15 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
     int64_t r2 = 0, r3 = 0;
     node_pair(bF, zFGH[0], bG, zFGH[1], r2, r3, P2, Q2, P3, Q3);      // PLUQ(F), PLUQ(G)
 
-    perm_rows(gi + r1, gj, k - r1, r1, P2);                    // M1 <- P2^T M1
-    perm_rows(gi + k, gj, m - k, r1, P3);                      // E  <- P3^T E
-    perm_cols(gi, gj + h, r1, n - h, Q2);                      // D  <- D Q2^T
-    perm_cols(gi, gj + r1, r1, h - r1, Q3);                    // V1 <- V1 Q3^T
-    if (zFGH[2] != Z_ZERO) {
-        perm_rows(gi + k, gj + h, m - k, n - h, P3);           // H <- P3^T H Q2^T
-        perm_cols(gi + k, gj + h, m - k, n - h, Q2);
+    {
+        // five disjoint blocks: rows [r1, k) and [k, m) of columns [0, r1),
+        // rows [0, r1) of columns [h, n) and [r1, h), and H
+        PermJob pj[5] = {{gi + r1, gj, k - r1, r1, &P2, nullptr},      // M1 <- P2^T M1
+                         {gi + k, gj, m - k, r1, &P3, nullptr},        // E  <- P3^T E
+                         {gi, gj + h, r1, n - h, nullptr, &Q2},        // D  <- D Q2^T
+                         {gi, gj + r1, r1, h - r1, nullptr, &Q3},      // V1 <- V1 Q3^T
+                         {gi + k, gj + h, m - k, n - h, &P3, &Q2}};    // H  <- P3^T H Q2^T
+        perm_batch(pj, zFGH[2] != Z_ZERO ? 5 : 4);
     }
 
     // R = H4 - K V2 - M3 O after the solves
@@ -867,10 +934,14 @@ int64_t Ctx::node(int64_t gi, int64_t gj, int64_t m, int64_t n, Zero z, std::vec
 
     std::vector<int32_t> P4, Q4;
     const int64_t r4 = node(bR.i, bR.j, bR.m, bR.n, zR, P4, Q4);       // PLUQ(R)
-    perm_rows(gi + k + r3, gj, m - k - r3, r1 + r3, P4);               // P4^T [E2 M3]
-    perm_rows(gi + k + r3, gj + h, m - k - r3, r2, P4);                // P4^T K
-    perm_cols(gi, gj + h + r2, r1 + r2, n - h - r2, Q4);               // [D2; V2] Q4^T
-    perm_cols(gi + k, gj + h + r2, r3, n - h - r2, Q4);                // O Q4^T
+    {
+        // disjoint: r1 + r3 <= h and r1 + r2 <= k
+        PermJob pj[4] = {{gi + k + r3, gj, m - k - r3, r1 + r3, &P4, nullptr},       // P4^T [E2 M3]
+                         {gi + k + r3, gj + h, m - k - r3, r2, &P4, nullptr},        // P4^T K
+                         {gi, gj + h + r2, r1 + r2, n - h - r2, nullptr, &Q4},       // [D2; V2] Q4^T
+                         {gi + k, gj + h + r2, r3, n - h - r2, nullptr, &Q4}};       // O Q4^T
+        perm_batch(pj, 4);
+    }
 
     // S^T A T^T
     {

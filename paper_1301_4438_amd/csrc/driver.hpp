@@ -75,6 +75,14 @@ struct Blk {
     int64_t i, j, m, n;
 };
 
+// One permutation of a node's block: the nr x nc block at (gi, gj) gets new
+// row t = old row (*rmap)[t] and new column t = old column (*cmap)[t]
+// (either map may be null).
+struct PermJob {
+    int64_t gi, gj, nr, nc;
+    const std::vector<int32_t> *rmap, *cmap;
+};
+
 // Layout of the int32 status area in device workspace.
 constexpr int64_t STAT_FLAG = 0;     // 8 zero-flag slots
 constexpr int64_t STAT_SPEC = 8;     // sticky flag: a speculated base case failed
@@ -196,6 +204,9 @@ struct Ctx {
     void read_status(int64_t offset, int64_t count);
     void perm_rows(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
     void perm_cols(int64_t gi, int64_t gj, int64_t nr, int64_t nc, const std::vector<int32_t> &map);
+    // Permutations of disjoint blocks applied together: one map upload, one
+    // gather launch into the scratch and one copy back per group of jobs.
+    void perm_batch(PermJob *jobs, int nj);
     void mm(MMProblem *probs, int n);
     void mm_launch(MMProblem *probs, int n);   // the classical kernel of the form, no splitting
     bool mm_i8(const MMProblem &pb);

@@ -3,6 +3,9 @@
 // the all-zero test of a block (a zero block returns rank 0 with identity
 // permutations without recursing), and the optional input range check.
 // All are HBM-bound: one coalesced pass over the block.
+#include <algorithm>
+#include <climits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -48,6 +51,57 @@ __global__ __launch_bounds__(PTHREADS) void rangescan_kernel(const T *A, int64_t
         bad |= !(v >= 0.0 && v < p && v == floor(v));
     }
     if (bad) *flag = gen;
+}
+
+// Several gathers of disjoint blocks in one launch: job q owns work-groups
+// [blockStart_q, blockStart_q + colBlocks_q * rowBlocks_q); work-group b of
+// a job covers 256 columns (b % colBlocks) and the rows b / colBlocks,
+// + rowBlocks, ...  dst[i][j] = src[rmap ? rmap[i] : i][cmap ? cmap[j] : j].
+template <typename T>
+__global__ __launch_bounds__(PTHREADS) void gather_jobs_kernel(const GatherJobs args) {
+    int q = 0;
+#pragma unroll
+    for (int t = 1; t < GATHER_MAX_JOBS; ++t)
+        if (t < args.count && (int)blockIdx.x >= args.job[t].blockStart) q = t;
+    const GatherJob &J = args.job[q];
+    const int b = (int)blockIdx.x - J.blockStart;
+    const int64_t j = (int64_t)(b % J.colBlocks) * PTHREADS + threadIdx.x;
+    if (j >= J.cols) return;
+    const T *src = (const T *)J.src;
+    T *dst = (T *)J.dst;
+    const int64_t sj = J.cmap ? (int64_t)J.cmap[j] : j;
+    for (int64_t i = b / J.colBlocks; i < J.rows; i += J.rowBlocks) {
+        const int64_t si = J.rmap ? (int64_t)J.rmap[i] : i;
+        dst[i * J.ldd + j] = src[si * J.lds + sj];
+    }
+}
+
+hipError_t launch_gather_jobs(int dtype, GatherJob *jobs, int njobs, hipStream_t st) {
+    if (njobs <= 0) return hipSuccess;
+    if (njobs > GATHER_MAX_JOBS) return hipErrorInvalidValue;
+    GatherJobs a;
+    a.count = 0;
+    int64_t total = 0;
+    for (int q = 0; q < njobs; ++q) {
+        GatherJob J = jobs[q];
+        if (J.rows <= 0 || J.cols <= 0) continue;
+        J.colBlocks = (int32_t)cdiv64(J.cols, PTHREADS);
+        // enough row-blocks to fill the GPU, capped by the row count
+        int64_t rb = (4096 + J.colBlocks - 1) / J.colBlocks;
+        J.rowBlocks = (int32_t)std::min<int64_t>(std::max<int64_t>(rb, 1), J.rows);
+        J.blockStart = (int32_t)total;
+        total += (int64_t)J.colBlocks * J.rowBlocks;
+        a.job[a.count++] = J;
+    }
+    if (a.count == 0) return hipSuccess;
+    if (total > INT32_MAX) return hipErrorInvalidValue;
+    switch (dtype) {
+    case DT_I64: PLUQ_LAUNCH(gather_jobs_kernel<int64_t>, dim3((unsigned)total), dim3(PTHREADS), 0, st, a); break;
+    case DT_F64: PLUQ_LAUNCH(gather_jobs_kernel<double>, dim3((unsigned)total), dim3(PTHREADS), 0, st, a); break;
+    case DT_I32: PLUQ_LAUNCH(gather_jobs_kernel<int32_t>, dim3((unsigned)total), dim3(PTHREADS), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 static dim3 grid2d(int64_t rows, int64_t cols) {

@@ -115,6 +115,25 @@ hipError_t launch_gather2d(int dtype, const void *src, int64_t lds, void *dst, i
                            int64_t rows, int64_t cols, const int32_t *rmap,
                            const int32_t *cmap, hipStream_t st);
 
+// Up to GATHER_MAX_JOBS gathers in one launch (dst[i][j] =
+// src[rmap ? rmap[i] : i][cmap ? cmap[j] : j], rows x cols each); the jobs'
+// destinations must not overlap each other's sources or destinations.
+constexpr int GATHER_MAX_JOBS = 8;
+struct GatherJob {
+    const void *src;
+    int64_t lds;
+    void *dst;
+    int64_t ldd;
+    int64_t rows, cols;
+    const int32_t *rmap, *cmap;
+    int32_t blockStart, colBlocks, rowBlocks;   // filled by the launcher
+};
+struct GatherJobs {
+    GatherJob job[GATHER_MAX_JOBS];
+    int32_t count;
+};
+hipError_t launch_gather_jobs(int dtype, GatherJob *jobs, int njobs, hipStream_t st);
+
 // *flag = gen if any element of the rows x cols block is non-zero.
 hipError_t launch_zscan(int dtype, const void *A, int64_t lda, int64_t rows, int64_t cols,
                         int32_t *flag, int32_t gen, hipStream_t st);
