@@ -9,8 +9,9 @@
 //     A.B = 2^16 S2 + 2^8 S1 + S0,
 //     S0 = A0.B0,  S1 = A0.B1 + A1.B0,  S2 = A1.B1,
 // where every term is at most 2^14 in magnitude, so for an inner dimension
-// of at most KMAX_I8 = 4096 (one launch) |S1| < 2^27 and the recombination
-// 2^16 S2 + 2^8 S1 + S0 is below 2^43: it is formed exactly in float64,
+// of at most KMAX_I8 = 16384 (one launch) |S1| <= 2^29 (int32 holds it) and
+// the recombination 2^16 S2 + 2^8 S1 + S0 is below 2^45: it is formed
+// exactly in float64,
 // subtracted from C and reduced once per output (delayed reduction,
 // Section 6).  Pivot inversion and everything outside MM stay in float64.
 //

@@ -60,7 +60,9 @@ struct SplitJob {
     int32_t blockStart;   // filled by the launcher
 };
 constexpr int SPLIT_MAX_JOBS = 4;
-constexpr int KMAX_I8 = 4096;   // inner dimension of one INT8 launch
+// inner dimension of one INT8 launch: the middle limb sum, at most
+// 2 KMAX_I8 2^14 in magnitude, must fit int32
+constexpr int KMAX_I8 = 16384;
 hipError_t launch_limb_split(int dtype, SplitJob *jobs, int njobs, double p, hipStream_t st);
 // C (M x N, ldc) <- C - sum over the Kp inner positions of the digit planes
 // a (M rows of lda bytes) and b (N rows of ldb bytes), mod p; nzflag as in
