@@ -181,29 +181,42 @@ __global__ __launch_bounds__(256) void trsm_diag_inv_pair_kernel(const T *Lm, in
 // products when RED16, p above about 2^23.5), never behind a run-time test
 // between matrix-core operations.  Rows past r contribute zeros (W' is zero
 // there), right-hand sides past nst are computed on zeros and not stored.
-constexpr int TRSM_STRIP = 16;
-
+// A work-group solves a strip of 16 NT right-hand sides: each wave owns NT
+// 16 x 16 matrix-core tiles of each 64-row block, which share every operand
+// block loaded (NT = 2 when that still gives enough work-groups).
+template <int NT>
 struct LeafSmem {
-    double Xs[TRSM_FUSE_MAX][TRSM_STRIP + 1];   // solved strip (symmetric)
-    double Acc[64][TRSM_STRIP + 1];              // B'_q - sum L' X (symmetric)
-    double Ls[2][64][65];                        // operand blocks (negated symmetric)
+    static constexpr int S = 16 * NT;   // right-hand sides of the strip
+    double Xs[TRSM_FUSE_MAX][S + 1];    // solved strip (symmetric)
+    double Acc[64][S + 1];              // B'_q - sum L' X (symmetric)
+    double Ls[2][64][65];               // operand blocks (negated symmetric)
 };
+// work-groups for nst right-hand sides at NT tiles per wave
+static inline int leaf_groups(int64_t nst, int nt) { return (int)cdiv64(nst, 16 * nt); }
+// NT = 2 when strips of 32 still give at least this many work-groups
+constexpr int LEAF_WIDE_MIN_GROUPS = 256;
 
 // Work-group body for strip `blk`; the LDS comes from the caller.
-template <typename T, bool UPPER, bool RED16>
+template <typename T, bool UPPER, bool RED16, int NT>
 __device__ __forceinline__ void trsm_leaf_body(const T *Tm, int64_t ldt, int r, T *B, int64_t ldb, int nst,
-                                               const T *W, ModP mod, int kchunk, int blk, LeafSmem &sm) {
+                                               const T *W, ModP mod, int kchunk, int blk, LeafSmem<NT> &sm) {
     typedef double v4d __attribute__((ext_vector_type(4)));
+    constexpr int S = LeafSmem<NT>::S;
     auto &Xs = sm.Xs;
     auto &Acc = sm.Acc;
     auto &Ls = sm.Ls;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int c0 = blk * TRSM_STRIP;
-    const int col = lane & 15;                 // right-hand side within the strip
+    const int c0 = blk * S;
+    const int col = lane & 15;                 // right-hand side within a 16-wide tile
     const int kl = lane >> 4;                  // k offset of this lane's operand
     const int nb = (r + 63) / 64;
-    const bool cval = c0 + col < nst;
-    const int ccl = cval ? c0 + col : nst - 1; // clamped right-hand side (loads stay in range)
+    bool cval[NT];
+    int ccl[NT];                               // clamped right-hand sides (loads stay in range)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        cval[t] = c0 + 16 * t + col < nst;
+        ccl[t] = cval[t] ? c0 + 16 * t + col : nst - 1;
+    }
 
     // Job (q, j), j <= q: j < q is L'_qj, j == q is W'_q.  Thread tid moves
     // elements e = tid + 256 m, m < 16, of the 64 x 64 block: memory row
@@ -255,44 +268,51 @@ __device__ __forceinline__ void trsm_leaf_body(const T *Tm, int64_t ldt, int r, 
             x[3][v] = 0.0;
         }
     };
-    // one 64-deep product: A operand from Ls[buf], B operand from rows
-    // [kb, kb + 64) of the LDS array bs
-    auto mfma_job = [&](int buf, const double (*bs)[TRSM_STRIP + 1], int kb, v4d *x) {
+    // one 64-deep product: A operand from Ls[buf] (shared by the NT tiles),
+    // B operands from rows [kb, kb + 64) of the LDS array bs
+    auto mfma_job = [&](int buf, const double (*bs)[S + 1], int kb, v4d (*x)[4]) {
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
             const double av = Ls[buf][16 * wv + col][4 * ks + kl];
-            const double bv = bs[kb + 4 * ks + kl][col];
-            x[ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x[ks & 3], 0, 0, 0);
-            if (RED16 && (ks & 3) == 3) reduce4(x);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double bv = bs[kb + 4 * ks + kl][16 * t + col];
+                x[t][ks & 3] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, x[t][ks & 3], 0, 0, 0);
+                if (RED16 && (ks & 3) == 3) reduce4(x[t]);
+            }
         }
     };
 
-    T bq[4];
+    T bq[NT][4];
     auto load_b = [&](int q) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = 64 * q + 16 * wv + kl + 4 * v, ic = i < r ? i : r - 1;
-            bq[v] = UPPER ? B[(int64_t)ccl * ldb + ic] : B[(int64_t)ic * ldb + ccl];
-        }
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 64 * q + 16 * wv + kl + 4 * v, ic = i < r ? i : r - 1;
+                bq[t][v] = UPPER ? B[(int64_t)ccl[t] * ldb + ic] : B[(int64_t)ic * ldb + ccl[t]];
+            }
     };
     // Jobs run as one flat sequence (q, j) = (0, 0), (1, 0), (1, 1), (2, 0),
     // ...; three register sets rotate (the loop is unrolled by three), so the
     // loads of job n + 2 are issued before job n is stored and have two whole
     // jobs' time to arrive (one job is shorter than a load from memory).
     T ra[16], rb[16], rc[16];
-    v4d x[4];
+    v4d x[NT][4];
     int buf = 0, kacc = 0;
     auto do_job = [&](int q, int j, T (&cur)[16], T (&nxt)[16], int q2, int j2) {
         const int i0 = 64 * q;
         if (j == 0) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + 16 * wv + kl + 4 * v;
-                x[0][v] = (i < r && cval) ? to_f64(bq[v]) : 0.0;
-                x[1][v] = 0.0;
-                x[2][v] = 0.0;
-                x[3][v] = 0.0;
-            }
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + 16 * wv + kl + 4 * v;
+                    x[t][0][v] = (i < r && cval[t]) ? to_f64(bq[t][v]) : 0.0;
+                    x[t][1][v] = 0.0;
+                    x[t][2][v] = 0.0;
+                    x[t][3][v] = 0.0;
+                }
             if (q + 1 < nb) load_b(q + 1);
             kacc = 0;
         }
@@ -300,31 +320,42 @@ __device__ __forceinline__ void trsm_leaf_body(const T *Tm, int64_t ldt, int r, 
         store_job(q, j, buf, cur);
         if (j == q) {
             // acc = B'_q - sum L' X, reduced: the W job's right operand
-            reduce4(x);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const double sv = to_sym(x[0][v], mod);
-                x[0][v] = sv;
-                Acc[16 * wv + kl + 4 * v][col] = sv;
+            for (int t = 0; t < NT; ++t) {
+                reduce4(x[t]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double sv = to_sym(x[t][0][v], mod);
+                    x[t][0][v] = sv;
+                    Acc[16 * wv + kl + 4 * v][16 * t + col] = sv;
+                }
             }
             kacc = 0;
         }
         __syncthreads();
-        if (!RED16 && kacc + 64 > kchunk) { reduce4(x); kacc = 0; }
+        if (!RED16 && kacc + 64 > kchunk) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) reduce4(x[t]);
+            kacc = 0;
+        }
         if (j < q) mfma_job(buf, Xs, 64 * j, x);
         else mfma_job(buf, Acc, 0, x);
         kacc += 64;
         buf ^= 1;
         if (j == q) {
-            reduce4(x);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + 16 * wv + kl + 4 * v;   // < 64 nb <= TRSM_FUSE_MAX
-                const double y = x[0][v];
-                Xs[i][col] = (i < r) ? to_sym(y, mod) : 0.0;
-                if (i < r && cval) {
-                    if (UPPER) B[(int64_t)(c0 + col) * ldb + i] = from_f64<T>(y);
-                    else B[(int64_t)i * ldb + c0 + col] = from_f64<T>(y);
+            for (int t = 0; t < NT; ++t) {
+                reduce4(x[t]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = i0 + 16 * wv + kl + 4 * v;   // < 64 nb <= TRSM_FUSE_MAX
+                    const double y = x[t][0][v];
+                    const int c = 16 * t + col;
+                    Xs[i][c] = (i < r) ? to_sym(y, mod) : 0.0;
+                    if (i < r && cval[t]) {
+                        if (UPPER) B[(int64_t)(c0 + c) * ldb + i] = from_f64<T>(y);
+                        else B[(int64_t)i * ldb + c0 + c] = from_f64<T>(y);
+                    }
                 }
             }
         }
@@ -358,27 +389,27 @@ __device__ __forceinline__ void trsm_leaf_body(const T *Tm, int64_t ldt, int r, 
     }
 }
 
-template <typename T, bool UPPER, bool RED16>
+template <typename T, bool UPPER, bool RED16, int NT>
 __global__ __launch_bounds__(256) void trsm_leaf_kernel(const T *Tm, int64_t ldt, int r, T *B, int64_t ldb,
                                                         int nst, const T *W, ModP mod, int kchunk) {
-    __shared__ LeafSmem sm;
-    trsm_leaf_body<T, UPPER, RED16>(Tm, ldt, r, B, ldb, nst, W, mod, kchunk, blockIdx.x, sm);
+    __shared__ LeafSmem<NT> sm;
+    trsm_leaf_body<T, UPPER, RED16, NT>(Tm, ldt, r, B, ldb, nst, W, mod, kchunk, blockIdx.x, sm);
 }
 
 // The two leaf solves of a recursion node in one launch, L X = BD (lower,
 // ncols right-hand sides) and X U = BE (upper, nrows right-hand sides), with
 // triangles of the same order: work-groups [0, gD) take strips of BD, the
 // rest strips of BE.
-template <typename T, bool RED16>
+template <typename T, bool RED16, int NT>
 __global__ __launch_bounds__(256) void trsm_leaf_pair_kernel(const T *Lm, int64_t ldl, const T *Um, int64_t ldu, int r,
                                                              T *BD, int64_t ldbd, int ncols, T *BE, int64_t ldbe,
                                                              int nrows, const T *WL, const T *WU, ModP mod, int kchunk,
                                                              int gD) {
-    __shared__ LeafSmem sm;
+    __shared__ LeafSmem<NT> sm;
     if ((int)blockIdx.x < gD)
-        trsm_leaf_body<T, false, RED16>(Lm, ldl, r, BD, ldbd, ncols, WL, mod, kchunk, blockIdx.x, sm);
+        trsm_leaf_body<T, false, RED16, NT>(Lm, ldl, r, BD, ldbd, ncols, WL, mod, kchunk, blockIdx.x, sm);
     else
-        trsm_leaf_body<T, true, RED16>(Um, ldu, r, BE, ldbe, nrows, WU, mod, kchunk, blockIdx.x - gD, sm);
+        trsm_leaf_body<T, true, RED16, NT>(Um, ldu, r, BE, ldbe, nrows, WU, mod, kchunk, blockIdx.x - gD, sm);
 }
 
 static ModP make_mod(double p) {
@@ -415,17 +446,21 @@ hipError_t launch_trsm_diag_inv(int dtype, int side, const void *Tm, int64_t ldt
 template <typename T>
 static hipError_t leaf_t(int side, const void *Tm, int64_t ldt, int r, void *B, int64_t ldb, int nst,
                          const void *W, double p, int kchunk, hipStream_t st) {
-    const dim3 grid((unsigned)cdiv64(nst, TRSM_STRIP));
+    const int nt = leaf_groups(nst, 2) >= LEAF_WIDE_MIN_GROUPS ? 2 : 1;
+    const dim3 grid((unsigned)leaf_groups(nst, nt));
     const ModP md = make_mod(p);
-#define PLUQ_LEAF(U, R16)                                                                              \
-    PLUQ_LAUNCH((trsm_leaf_kernel<T, U, R16>), grid, dim3(256), 0, st, (const T *)Tm, ldt, r, (T *)B, ldb, nst, \
+#define PLUQ_LEAF(U, R16, NT)                                                                              \
+    PLUQ_LAUNCH((trsm_leaf_kernel<T, U, R16, NT>), grid, dim3(256), 0, st, (const T *)Tm, ldt, r, (T *)B, ldb, nst, \
                 (const T *)W, md, kchunk)
+#define PLUQ_LEAF_NT(U, R16) \
+    if (nt == 2) PLUQ_LEAF(U, R16, 2); else PLUQ_LEAF(U, R16, 1);
     const bool r16 = kchunk < 64;
     if (side == 0) {
-        if (r16) PLUQ_LEAF(false, true); else PLUQ_LEAF(false, false);
+        if (r16) { PLUQ_LEAF_NT(false, true) } else { PLUQ_LEAF_NT(false, false) }
     } else {
-        if (r16) PLUQ_LEAF(true, true); else PLUQ_LEAF(true, false);
+        if (r16) { PLUQ_LEAF_NT(true, true) } else { PLUQ_LEAF_NT(true, false) }
     }
+#undef PLUQ_LEAF_NT
 #undef PLUQ_LEAF
     return hipGetLastError();
 }
@@ -455,14 +490,18 @@ template <typename T>
 static hipError_t leaf_pair_t(const void *Lm, int64_t ldl, const void *Um, int64_t ldu, int r, void *BD, int64_t ldbd,
                               int ncols, void *BE, int64_t ldbe, int nrows, const void *WL, const void *WU, double p,
                               int kchunk, hipStream_t st) {
-    const int gD = (int)cdiv64(ncols, TRSM_STRIP), gE = (int)cdiv64(nrows, TRSM_STRIP);
+    const int nt = leaf_groups(ncols, 2) + leaf_groups(nrows, 2) >= LEAF_WIDE_MIN_GROUPS ? 2 : 1;
+    const int gD = leaf_groups(ncols, nt), gE = leaf_groups(nrows, nt);
     const ModP md = make_mod(p);
-#define PLUQ_LEAF_PAIR(R16)                                                                                     \
-    PLUQ_LAUNCH((trsm_leaf_pair_kernel<T, R16>), dim3((unsigned)(gD + gE)), dim3(256), 0, st, (const T *)Lm, ldl, \
+#define PLUQ_LEAF_PAIR(R16, NT)                                                                                     \
+    PLUQ_LAUNCH((trsm_leaf_pair_kernel<T, R16, NT>), dim3((unsigned)(gD + gE)), dim3(256), 0, st, (const T *)Lm, ldl, \
                 (const T *)Um, ldu, r, (T *)BD, ldbd, ncols, (T *)BE, ldbe, nrows, (const T *)WL, (const T *)WU, md, \
                 kchunk, gD)
-    if (kchunk < 64) PLUQ_LEAF_PAIR(true);
-    else PLUQ_LEAF_PAIR(false);
+    if (kchunk < 64) {
+        if (nt == 2) PLUQ_LEAF_PAIR(true, 2); else PLUQ_LEAF_PAIR(true, 1);
+    } else {
+        if (nt == 2) PLUQ_LEAF_PAIR(false, 2); else PLUQ_LEAF_PAIR(false, 1);
+    }
 #undef PLUQ_LEAF_PAIR
     return hipGetLastError();
 }
