@@ -36,6 +36,8 @@ namespace pluq {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+constexpr int MM_GROUP = 8;   // tile rows per group of the tile order
+
 // Accumulator vector and output-row layout of the matrix-core instruction
 // used for compute type CT.  Lane `lane` holds, in element v of its 16 x 16
 // block, row row(lane, v) and column lane % 16.
@@ -73,17 +75,26 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
     __shared__ CT As[BM * PA];
     __shared__ CT Bs[BK * PB];
 
-    const int tile = blockIdx.x;
+    // work-group -> tile: the work-groups one XCD runs (dispatch is
+    // round-robin over the 8 XCDs) take a contiguous range of the launch's
+    // tiles, and within a problem the tiles go in groups of MM_GROUP tile
+    // rows, column by column, so the A and B panels that tiles running
+    // together share stay in one XCD's L2 (a bijection for any tile count)
+    const int tiles = (int)gridDim.x;
+    const int xcd = (int)blockIdx.x % 8, qx = (int)blockIdx.x / 8;
+    const int tile = xcd * (tiles / 8) + min(xcd, tiles % 8) + qx;
     int pi = 0;
 #pragma unroll
     for (int q = 1; q < MM_MAX_PROBLEMS; ++q)
         if (q < args.count && tile >= args.prob[q].tileStart) pi = q;
     const MMProblem &P = args.prob[pi];
     const ModP mod = args.mod;
-    const int t = tile - P.tileStart;
-    const int row0 = (t / P.tilesN) * BM;
-    const int col0 = (t % P.tilesN) * BN;
     const int M = P.M, N = P.N;
+    const int t = tile - P.tileStart, tilesN = P.tilesN, tilesM = (M + BM - 1) / BM;
+    const int gsz = MM_GROUP * tilesN, grp = t / gsz;
+    const int gr0 = grp * MM_GROUP, grows = min(tilesM - gr0, MM_GROUP);
+    const int row0 = (gr0 + (t - grp * gsz) % grows) * BM;
+    const int col0 = ((t - grp * gsz) / grows) * BN;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
