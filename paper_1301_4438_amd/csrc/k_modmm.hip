@@ -15,13 +15,16 @@
 // 2^25 in float64, p above about 2^10 in float32): the RED16 instances then
 // reduce after every 16 products, at fixed points inside the panel.
 //
-// Tiling: 256 threads = 4 waves in a 2 x 2 grid; each wave owns a
-// (BM/2) x (BN/2) sub-tile made of 16 x 16 blocks computed with
-// v_mfma_f64_16x16x4_f64.  Panels of depth BK are staged in LDS (A row-major,
-// B row-major, both padded); global loads are lane-contiguous row segments;
-// the next panel is fetched into registers while the current one is used.
-// 64 x 64 and 32 x 32 tiles use BK = 64, so an update with K <= 64 (the
-// deep Schur updates) needs a single load phase.
+// Tiling: the 128 x 128 tile runs 512 threads = 8 waves in a 2 x 4 grid,
+// each wave owning a 64 x 32 sub-tile (two waves per SIMD; a 64 x 64 wave
+// tile's accumulators would leave one), with double-buffered panels and one
+// barrier per panel; the smaller tiles run 256 threads = 4 waves in a 2 x 2
+// grid with one panel buffer.  Sub-tiles are made of 16 x 16 blocks computed
+// with v_mfma_f64_16x16x4_f64.  Panels of depth BK are staged in LDS (A
+// row-major, B row-major, both padded); global loads are lane-contiguous row
+// segments; the next panel is fetched into registers while the current one is
+// used.  64 x 64 and 32 x 32 tiles use BK = 64, so an update with K <= 64
+// (the deep Schur updates) needs a single load phase.
 //
 // The same kernel in float32 (CT = float, v_mfma_f32_16x16x4_f32) is the
 // FP32 form for small moduli: a float32 sum of integers is exact while it
@@ -64,16 +67,23 @@ struct MMArgs {
     ModP mod;
 };
 
-template <typename T, typename CT, int BM, int BN, int BK, bool RED16>
-__global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
+// NTH threads: 2 x (NTH / 128) waves, each owning a (BM / 2) x (BN / (NTH /
+// 128)) sub-tile.  DB: the A and B panels are double-buffered in LDS (one
+// barrier per panel: the next panel is stored into the other buffer after
+// the current one's products); otherwise one buffer and two barriers.
+template <typename T, typename CT, int BM, int BN, int BK, bool RED16, int NTH, bool DB>
+__global__ __launch_bounds__(NTH) void modmm_kernel(const MMArgs args) {
     typedef MfmaTraits<CT> MT;
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int WNW = NTH / 128;            // waves along N
+    constexpr int WM = BM / 2, WN = BN / WNW;
     constexpr int FM = WM / 16, FN = WN / 16;
-    constexpr int ELA = BM * BK / 256;   // A elements loaded per thread and panel
-    constexpr int ELB = BN * BK / 256;   // B elements loaded per thread and panel
+    constexpr int ELA = BM * BK / NTH;   // A elements loaded per thread and panel
+    constexpr int ELB = BN * BK / NTH;   // B elements loaded per thread and panel
     constexpr int PA = BK + 1, PB = BN + 1;
-    __shared__ CT As[BM * PA];
-    __shared__ CT Bs[BK * PB];
+    constexpr int NB = DB ? 2 : 1;
+    static_assert(FN >= 1 && ELA >= 1 && ELB >= 1 && ELA <= 32 && ELB <= 32, "tile shape");
+    __shared__ CT As[NB][BM * PA];
+    __shared__ CT Bs[NB][BK * PB];
 
     // work-group -> tile: the work-groups one XCD runs (dispatch is
     // round-robin over the 8 XCDs) take a contiguous range of the launch's
@@ -99,8 +109,8 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wm0 = (wave >> 1) * WM;
-    const int wn0 = (wave & 1) * WN;
+    const int wm0 = (wave / WNW) * WM;
+    const int wn0 = (wave % WNW) * WN;
 
     // accumulator <- C (canonical).
     T *C = (T *)P.C;
@@ -138,17 +148,32 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
         mb = 0;
 #pragma unroll
         for (int e = 0; e < ELA; ++e) {
-            const int idx = tid + 256 * e;
+            const int idx = tid + NTH * e;
             const int gr = row0 + idx / BK, gk = k0 + idx % BK;
             ma |= (uint32_t)(gr < M && gk < K) << e;
             ra[e] = A[(int64_t)min(gr, M - 1) * lda + min(gk, K - 1)];
         }
 #pragma unroll
         for (int e = 0; e < ELB; ++e) {
-            const int idx = tid + 256 * e;
+            const int idx = tid + NTH * e;
             const int gk = k0 + idx / BN, gc = col0 + idx % BN;
             mb |= (uint32_t)(gk < K && gc < N) << e;
             rb[e] = B[(int64_t)min(gk, K - 1) * ldb + min(gc, N - 1)];
+        }
+    };
+    // the loaded panel, converted (A negated), into LDS buffer buf
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < ELA; ++e) {
+            const int idx = tid + NTH * e;
+            const CT v = (CT)-to_sym(to_f64(ra[e]), mod);
+            As[buf][(idx / BK) * PA + idx % BK] = ((ma >> e) & 1u) ? v : (CT)0;
+        }
+#pragma unroll
+        for (int e = 0; e < ELB; ++e) {
+            const int idx = tid + NTH * e;
+            const CT v = (CT)to_sym(to_f64(rb[e]), mod);
+            Bs[buf][(idx / BN) * PB + idx % BN] = ((mb >> e) & 1u) ? v : (CT)0;
         }
     };
 
@@ -162,35 +187,15 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
     };
 
     int kacc = 0;
-    if (steps > 0) load_step(0);
-    for (int s = 0; s < steps; ++s) {
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < ELA; ++e) {
-            const int idx = tid + 256 * e;
-            const CT v = (CT)-to_sym(to_f64(ra[e]), mod);
-            As[(idx / BK) * PA + idx % BK] = ((ma >> e) & 1u) ? v : (CT)0;
-        }
-#pragma unroll
-        for (int e = 0; e < ELB; ++e) {
-            const int idx = tid + 256 * e;
-            const CT v = (CT)to_sym(to_f64(rb[e]), mod);
-            Bs[(idx / BN) * PB + idx % BN] = ((mb >> e) & 1u) ? v : (CT)0;
-        }
-        __syncthreads();
-        if (s + 1 < steps) load_step(s + 1);
-        if (!RED16 && kacc + BK > args.kchunk) {
-            reduce_acc();
-            kacc = 0;
-        }
+    auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
         for (int ks = 0; ks < BK / 4; ++ks) {
             const int kr = ks * 4 + (lane >> 4);
             CT a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = As[(wm0 + i * 16 + (lane & 15)) * PA + kr];
+            for (int i = 0; i < FM; ++i) a[i] = As[buf][(wm0 + i * 16 + (lane & 15)) * PA + kr];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = Bs[kr * PB + wn0 + j * 16 + (lane & 15)];
+            for (int j = 0; j < FN; ++j) b[j] = Bs[buf][kr * PB + wn0 + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -199,7 +204,42 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
             // 16 products since the last reduction: at most kchunk
             if (RED16 && (ks & 3) == 3) reduce_acc();
         }
-        kacc += BK;
+    };
+    if (DB) {
+        if (steps > 0) {
+            load_step(0);
+            stash(0);
+        }
+        __syncthreads();
+        for (int s = 0; s < steps; ++s) {
+            const int buf = s & 1;
+            // the next panel's loads are in flight during this one's
+            // products; it goes into the other buffer, which every wave
+            // finished reading before the barrier that ended the last step
+            if (s + 1 < steps) load_step(s + 1);
+            if (!RED16 && kacc + BK > args.kchunk) {
+                reduce_acc();
+                kacc = 0;
+            }
+            compute(buf);
+            kacc += BK;
+            if (s + 1 < steps) stash(buf ^ 1);
+            __syncthreads();
+        }
+    } else {
+        if (steps > 0) load_step(0);
+        for (int s = 0; s < steps; ++s) {
+            __syncthreads();
+            stash(0);
+            __syncthreads();
+            if (s + 1 < steps) load_step(s + 1);
+            if (!RED16 && kacc + BK > args.kchunk) {
+                reduce_acc();
+                kacc = 0;
+            }
+            compute(0);
+            kacc += BK;
+        }
     }
 
     bool nz = false;
@@ -220,22 +260,25 @@ __global__ __launch_bounds__(256) void modmm_kernel(const MMArgs args) {
     if (nz && P.nzflag) *P.nzflag = P.nzgen;
 }
 
-template <typename T, typename CT, int BM, int BN, int BK>
+template <typename T, typename CT, int BM, int BN, int BK, int NTH, bool DB>
 static hipError_t launch_t(MMArgs &args, int total, hipStream_t st) {
     if (args.kchunk < BK)
-        PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK, true>), dim3(total), dim3(256), 0, st, args);
+        PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK, true, NTH, DB>), dim3(total), dim3(NTH), 0, st, args);
     else
-        PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK, false>), dim3(total), dim3(256), 0, st, args);
+        PLUQ_LAUNCH((modmm_kernel<T, CT, BM, BN, BK, false, NTH, DB>), dim3(total), dim3(NTH), 0, st, args);
     return hipGetLastError();
 }
 
+// The large tile runs 8 waves of 64 x 32 with double-buffered panels: a
+// 64 x 64 wave tile's accumulators leave one wave per SIMD, with nothing to
+// cover the barriers and load waits; the small tiles keep 4 waves.
 template <typename T, typename CT>
 static hipError_t launch_dt(MMArgs &args, int bm, int bn, int total, hipStream_t st) {
-    if (bm == 128) return launch_t<T, CT, 128, 128, 32>(args, total, st);
-    if (bm == 64 && bn == 64) return launch_t<T, CT, 64, 64, 64>(args, total, st);
-    if (bm == 64) return launch_t<T, CT, 64, 32, 64>(args, total, st);
-    if (bn == 64) return launch_t<T, CT, 32, 64, 64>(args, total, st);
-    return launch_t<T, CT, 32, 32, 64>(args, total, st);
+    if (bm == 128) return launch_t<T, CT, 128, 128, 32, 512, true>(args, total, st);
+    if (bm == 64 && bn == 64) return launch_t<T, CT, 64, 64, 64, 256, false>(args, total, st);
+    if (bm == 64) return launch_t<T, CT, 64, 32, 64, 256, false>(args, total, st);
+    if (bn == 64) return launch_t<T, CT, 32, 64, 64, 256, false>(args, total, st);
+    return launch_t<T, CT, 32, 32, 64, 256, false>(args, total, st);
 }
 
 template <typename CT>
