@@ -98,8 +98,9 @@ typedef struct {
     int32_t no_speculation;     /* non-zero: no speculative first attempt (pluq_modp) and
                                    no room for it in pluq_workspace_size */
     int32_t branches;           /* concurrent recursion branches of pluq_modp: the calls
-                                   PLUQ(F) and PLUQ(G) of a node, both at least 256 x 256,
-                                   run side by side while a branch is free (0: 4; 1: none;
+                                   PLUQ(F) and PLUQ(G) of a node, both at least
+                                   pluq_tune.fork_min_dim (128) in each dimension,
+                                   run side by side while a branch is free (0: 8; 1: none;
                                    at most 16); each branch needs its own workspace share
                                    (pluq_workspace_size counts them); the result does not
                                    depend on it */
@@ -238,7 +239,7 @@ typedef struct {
     int32_t mm_tiles128;   /* an MM launch uses 128 x 128 tiles from this many such tiles on (0: 240) */
     int32_t mm_tiles64;    /* else 64 x 64 tiles from this many on, else 32 x 32 (0: 192) */
     int32_t cutoff;        /* base-case tile dimension, 16 .. 128 (0: 128) */
-    int32_t fork_min_dim;  /* PLUQ(F) || PLUQ(G) when both are at least this (0: 256) */
+    int32_t fork_min_dim;  /* PLUQ(F) || PLUQ(G) when both are at least this (0: 128) */
     int64_t i8_min_work;   /* INT8 form: updates below this many multiply-adds stay in FP64 (0: 2^26) */
     int32_t batch_panel;   /* batched form: panel width 8 or 16 (0: 8) */
     int32_t batch_groups;  /* batched form: work-groups per compute unit (0: 4 for panel 8, 2 for 16) */

@@ -150,8 +150,8 @@ constexpr size_t SPEC_MAX_BYTES = (size_t)1 << 30;
 
 // Concurrent recursion branches (PLUQ(F) || PLUQ(G)) by default, and the
 // smallest F and G (in each dimension) that are run side by side.
-constexpr int DEFAULT_BRANCHES = 4;
-constexpr int64_t FORK_MIN_DIM = 256;
+constexpr int DEFAULT_BRANCHES = 8;
+constexpr int64_t FORK_MIN_DIM = 128;
 
 // Diagonal-block inverses of a triangle of order r (TRSM).
 size_t trsm_w_bytes(int64_t r, size_t esz) {
