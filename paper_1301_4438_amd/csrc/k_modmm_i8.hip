@@ -66,10 +66,10 @@ __device__ __forceinline__ void digits(int v, int &d0, int &d1) {
     d1 = (v - d0) >> 8;   // exact: v - d0 is a multiple of 256
 }
 
-// Row job: source rows x K, inner dimension contiguous; thread = 8
-// consecutive entries of one row.  Transposed job: source K x rows (the
-// B operand, columns contiguous); a 64 x 64 tile per work-group goes through
-// LDS so that both the reads and the plane writes are contiguous.
+// Row job: source rows x K, inner dimension contiguous (the A operand).
+// Transposed job: source K x rows (the B operand, columns contiguous).  Both
+// take a 64 x 64 tile per work-group through LDS so that both the reads and
+// the plane writes are contiguous.
 template <typename T, int NL>
 __global__ __launch_bounds__(256) void limb_split_kernel(const SplitArgs args) {
     __shared__ int8_t tl[NL][64 * 68];
@@ -84,23 +84,40 @@ __global__ __launch_bounds__(256) void limb_split_kernel(const SplitArgs args) {
     const int thr = args.thr;
     const int tid = threadIdx.x;
     if (!J.trans) {
-        const int64_t groups_per_row = J.Kp / 8;
-        const int64_t g = (int64_t)b * 256 + tid;
-        if (g >= (int64_t)J.rows * groups_per_row) return;
-        const int row = (int)(g / groups_per_row);
-        const int k0 = (int)(g % groups_per_row) * 8;
-        uint64_t w0 = 0, w1 = 0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int k = k0 + e;
-            const double a = (k < J.K) ? to_f64(X[(int64_t)row * J.ld + k]) : 0.0;
+        // 64 rows x 64 inner positions per work-group: each load instruction
+        // reads 64 consecutive entries of one row; the digits go to LDS
+        // transposed (bytes of a row 68 apart, so the byte stores of a wave
+        // hit distinct banks) and each thread writes 16 digits of one row
+        const int tilesK = (int)(J.Kp / 64);
+        const int r0 = (b / tilesK) * 64, kb = (b % tilesK) * 64;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) {
+            const int idx = tid + 256 * e;
+            const int rr = idx >> 6, kk = idx & 63;
+            const int row = r0 + rr, k = kb + kk;
+            const double a = (k < J.K && row < J.rows) ? to_f64(X[(int64_t)row * J.ld + k]) : 0.0;
             int d0, d1;
             digits(shifted(a, thr, p), d0, d1);
-            w0 |= (uint64_t)(uint8_t)d0 << (8 * e);
-            w1 |= (uint64_t)(uint8_t)d1 << (8 * e);
+            tl[0][kk * 68 + rr] = (int8_t)d0;
+            if (NL == 2) tl[NL - 1][kk * 68 + rr] = (int8_t)d1;
         }
-        *(uint64_t *)(J.dst0 + (int64_t)row * J.ldd + k0) = w0;
-        if (NL == 2) *(uint64_t *)(J.dst1 + (int64_t)row * J.ldd + k0) = w1;
+        __syncthreads();
+        const int rr = tid >> 2, c = (tid & 3) * 16;
+        const int row = r0 + rr;
+        if (row < J.rows) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                v4i w;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int8_t *s0 = &tl[l][(c + 4 * q) * 68 + rr];
+                    w[q] = (int)((uint32_t)(uint8_t)s0[0] | ((uint32_t)(uint8_t)s0[68] << 8) |
+                                 ((uint32_t)(uint8_t)s0[136] << 16) | ((uint32_t)(uint8_t)s0[204] << 24));
+                }
+                int8_t *d = (l == 0 ? J.dst0 : J.dst1) + (int64_t)row * J.ldd + kb + c;
+                *(v4i *)d = w;
+            }
+        }
     } else {
         const int tilesK = (int)(J.Kp / 64);
         const int n0 = (b / tilesK) * 64, kb = (b % tilesK) * 64;
@@ -167,7 +184,7 @@ hipError_t launch_limb_split(int dtype, SplitJob *jobs, int njobs, double p, hip
         SplitJob &J = jobs[q];
         if (J.Kp % 64 || J.ldd % 16 || J.K > J.Kp) return hipErrorInvalidValue;
         J.blockStart = total;
-        const int64_t blocks = J.trans ? cdiv64(J.rows, 64) * (J.Kp / 64) : cdiv64((int64_t)J.rows * (J.Kp / 8), 256);
+        const int64_t blocks = cdiv64(J.rows, 64) * (J.Kp / 64);
         total += (int)blocks;
         a.job[q] = J;
     }
