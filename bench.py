@@ -61,9 +61,13 @@ CLASS_ROOF = {
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
 # `bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-comparisons`, each
 # scaled by what the counter reads for a plain device copy of known size in
-# the same run.  Valid only for the code the counters were taken on (sha256
-# prefix of the listed sources, comments removed); empty until measured.
-TRAFFIC = {}
+# the same run (a 2 GiB float64 copy: FETCH_SIZE x 1.99973, WRITE_SIZE x 1).
+# Valid only for the code the counters were taken on (sha256 prefix of the
+# listed sources, comments removed).
+TRAFFIC = {
+    "modmm_i8": {"sources": ["k_modmm_i8.hip", "kernels.hpp"], "source_sha256_16": "a6671e28241bcc27",
+                 "fetch_bytes_per_launch": 30060.9 * 1024 * 1.99973, "write_bytes_per_launch": 22096.9 * 1024},
+}
 
 
 def source_hash(files) -> str:
@@ -114,8 +118,10 @@ def roofline(prof: dict):
     t = TRAFFIC.get(cls)
     if t and source_hash(t["sources"]) == t["source_sha256_16"]:
         traffic = t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"]
+    alg_bytes = v["bytes"] / v["launches"]
     return {"bound": bound, "class": cls, "kernel": kernel, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic, "launches": v["launches"],
+            "frac": achieved / peak, "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+            "traffic_over_algorithmic_bytes": traffic / alg_bytes if traffic else None, "launches": v["launches"],
             "avg_launch_ms": v["ms"] / v["launches"], "device_ms_in_profiled_step": v["ms"],
             "algorithmic_work_per_launch": (v["bytes"] if bound == "hbm" else v["flops"]) / v["launches"],
             "work_unit": "bytes" if bound == "hbm" else ("int8 ops" if cls == "modmm_i8" else "flops")}
