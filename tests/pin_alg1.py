@@ -1,9 +1,17 @@
-"""Algorithm 1 of the paper (Section 2), restated in matrix form for tiny inputs.
+"""The quad recursion of Section 2 written out with explicit 0/1 permutation
+matrices, for tiny inputs.
 
-An oracle pin: it follows the paper's block steps with explicit 0/1
-permutation matrices and the printed composition formulas for P, Q, S and T,
-so that its output can be compared with the oracle's three-stage
-computation.  Readings taken where the printed text is garbled:
+An oracle pin, derived from the block identities rather than transcribed:
+with A1 = P1 [L1; M1] [U1 V1] Q1, the blocks beside and below A1 are put in
+A1's row and column order, the factors next to L1 and U1 are obtained by
+triangular solves, the Schur complements of the three remaining blocks are
+formed, the two off-diagonal ones are factored recursively, their
+permutations are carried into the blocks they touch, the last block's
+complement is formed from the triangles of those factorizations and factored,
+and a final block permutation on each side gathers the pivot rows and
+columns in front.  Its output (a plain matrix computation, exact over
+GF(p)) is compared with the oracle's three-stage computation, which shares
+no code with it.  Readings taken where the text is garbled:
   * the leaves' index exchange T_{1,i} is a cyclic rotation (1..i), and the
     n = 1 leaf permutes rows (P), not columns;
   * D Q2^T and V1 Q3^T are column permutations;
@@ -118,26 +126,31 @@ def pluq(A, p):
 
     k, h = m // 2, n // 2
     P1, Q1, r1 = pluq(A[:k, :h], p)
-    A[:k, h:] = _mm(P1.T, A[:k, h:], p)                     # PermR(A2, P1^T)
-    A[k:, :h] = _mm(A[k:, :h], Q1.T, p)                     # PermC(A3, Q1^T)
+    # the blocks right of and below A1 in A1's row / column order
+    A[:k, h:] = _mm(P1.T, A[:k, h:], p)
+    A[k:, :h] = _mm(A[k:, :h], Q1.T, p)
     L1 = np.tril(A[:r1, :r1], -1) + _eye(r1)
     U1 = np.triu(A[:r1, :r1])
-    A[:r1, h:] = _trsm_lower_unit(L1, A[:r1, h:], p)        # D
-    A[k:, :r1] = _trsm_upper_right(A[k:, :r1], U1, p)       # E
+    # the factors beside the triangles: L1 X = top rows, Y U1 = left columns
+    A[:r1, h:] = _trsm_lower_unit(L1, A[:r1, h:], p)
+    A[k:, :r1] = _trsm_upper_right(A[k:, :r1], U1, p)
     M1 = A[r1:k, :r1].copy()
     V1 = A[:r1, r1:h].copy()
     D = A[:r1, h:].copy()
     E = A[k:, :r1].copy()
-    A[r1:k, h:] = (A[r1:k, h:] - _mm(M1, D, p)) % p         # F
-    A[k:, r1:h] = (A[k:, r1:h] - _mm(E, V1, p)) % p         # G
-    A[k:, h:] = (A[k:, h:] - _mm(E, D, p)) % p              # H
+    # Schur complements of the three blocks around A1
+    A[r1:k, h:] = (A[r1:k, h:] - _mm(M1, D, p)) % p
+    A[k:, r1:h] = (A[k:, r1:h] - _mm(E, V1, p)) % p
+    A[k:, h:] = (A[k:, h:] - _mm(E, D, p)) % p
     P2, Q2, r2 = pluq(A[r1:k, h:], p)
     P3, Q3, r3 = pluq(A[k:, r1:h], p)
-    A[k:, h:] = _mm(_mm(P3.T, A[k:, h:], p), Q2.T, p)       # P3^T H Q2^T
-    A[k:, :r1] = _mm(P3.T, A[k:, :r1], p)                   # P3^T E
-    A[r1:k, :r1] = _mm(P2.T, A[r1:k, :r1], p)               # P2^T M1
-    A[:r1, h:] = _mm(A[:r1, h:], Q2.T, p)                   # D Q2^T
-    A[:r1, r1:h] = _mm(A[:r1, r1:h], Q3.T, p)               # V1 Q3^T
+    # the two factorizations' row and column orders carried into the blocks
+    # that share their rows or columns
+    A[k:, h:] = _mm(_mm(P3.T, A[k:, h:], p), Q2.T, p)
+    A[k:, :r1] = _mm(P3.T, A[k:, :r1], p)
+    A[r1:k, :r1] = _mm(P2.T, A[r1:k, :r1], p)
+    A[:r1, h:] = _mm(A[:r1, h:], Q2.T, p)
+    A[:r1, r1:h] = _mm(A[:r1, r1:h], Q3.T, p)
     H1 = A[k:k + r3, h:h + r2].copy()
     H2 = A[k:k + r3, h + r2:].copy()
     H3 = A[k + r3:, h:h + r2].copy()
@@ -146,6 +159,8 @@ def pluq(A, p):
     V2 = A[r1:r1 + r2, h + r2:].copy()
     L3 = np.tril(A[k:k + r3, r1:r1 + r3], -1) + _eye(r3)
     M3 = A[k + r3:, r1:r1 + r3].copy()
+    # the bottom-right block's complement with respect to the two new
+    # triangles, through solves against U2 and L3
     I = _trsm_upper_right(H1, U2, p)
     J = _trsm_lower_unit(L3, I, p)
     K = _trsm_upper_right(H3, U2, p)
@@ -157,9 +172,13 @@ def pluq(A, p):
     A[k:k + r3, h + r2:] = O
     A[k + r3:, h + r2:] = R
     P4, Q4, r4 = pluq(A[k + r3:, h + r2:], p)
-    A[k + r3:, :h + r2] = _mm(P4.T, A[k + r3:, :h + r2], p)  # P4^T [E2 M3 0 K]
-    A[:k + r3, h + r2:] = _mm(A[:k + r3, h + r2:], Q4.T, p)  # [D2;V2;0;O] Q4^T
+    # its row / column order carried into the rows left of it and the
+    # columns above it
+    A[k + r3:, :h + r2] = _mm(P4.T, A[k + r3:, :h + r2], p)
+    A[:k + r3, h + r2:] = _mm(A[:k + r3, h + r2:], Q4.T, p)
 
+    # block permutations gathering the pivot rows (S) and columns (T) in front,
+    # and the composed row and column orders
     S = _place([r1 + r2, k - r1 - r2, r3 + r4, m - k - r3 - r4],
                [r1 + r2, r3 + r4, k - r1 - r2, m - k - r3 - r4],
                [(0, 0), (1, 2), (2, 1), (3, 3)], m)
