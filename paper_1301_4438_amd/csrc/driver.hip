@@ -694,8 +694,107 @@ static void zorder_rec(const std::vector<int32_t> &rows, const std::vector<int32
     zorder_rec(minus(r_bot, rows3), minus(c_right, cols2), rpm_col, colpos, pr, pc, mark, stamp);  // R
 }
 
+// The same recursion for tiles of at most 128 rows and columns, on 128-bit
+// row and column sets (ascending index order is bit order) and fixed arrays:
+// no allocation per call.
+struct Set128 {
+    uint64_t lo = 0, hi = 0;
+};
+static inline int count128(const Set128 &a) { return __builtin_popcountll(a.lo) + __builtin_popcountll(a.hi); }
+static inline bool has128(const Set128 &a, int i) { return i < 64 ? (a.lo >> i) & 1u : (a.hi >> (i - 64)) & 1u; }
+static inline void add128(Set128 &a, int i) {
+    if (i < 64) a.lo |= 1ull << i;
+    else a.hi |= 1ull << (i - 64);
+}
+static inline Set128 minus128(const Set128 &a, const Set128 &b) { return Set128{a.lo & ~b.lo, a.hi & ~b.hi}; }
+// the k lowest members of a
+static inline uint64_t lowest64(uint64_t x, int k) {
+    if (k >= __builtin_popcountll(x)) return x;
+    // b: index of the (k+1)-th lowest member (it exists), found by halving the window
+    uint64_t y = x;
+    int b = 0;
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = __builtin_popcountll(y & ((1ull << w) - 1));
+        if (c <= k) {
+            k -= c;
+            y >>= w;
+            b += w;
+        }
+    }
+    return x & ((1ull << b) - 1);
+}
+static inline Set128 lowest128(const Set128 &a, int k) {
+    const int nlo = __builtin_popcountll(a.lo);
+    if (k <= nlo) return Set128{lowest64(a.lo, k), 0};
+    return Set128{a.lo, lowest64(a.hi, k - nlo)};
+}
+struct ZTile {
+    const int32_t *rpm_col;
+    int32_t pr[128], pc[128];
+    int np = 0;
+};
+static inline Set128 and128(const Set128 &a, const Set128 &b) { return Set128{a.lo & b.lo, a.hi & b.hi}; }
+static inline Set128 or128(const Set128 &a, const Set128 &b) { return Set128{a.lo | b.lo, a.hi | b.hi}; }
+static inline int top128(const Set128 &a) { return a.hi ? 127 - __builtin_clzll(a.hi) : 63 - __builtin_clzll(a.lo); }
+// Emits the pivots of R x C in the recursion's order and returns the sets of
+// their rows (rows) and columns (cols).  pc: the rows whose pivot column lies
+// in C, so the call's pivots are R & pc and the children's masks follow from
+// the pivots alone.
+static void zorder_tile(ZTile &z, const Set128 &R, const Set128 &C, const Set128 &pc, Set128 &rows, Set128 &cols) {
+    rows = Set128{};
+    cols = Set128{};
+    const Set128 piv = and128(R, pc);
+    if (!piv.lo && !piv.hi) return;
+    const int nr = count128(R), nc = count128(C);
+    if (nr == 1 || nc == 1) {
+        const int last = top128(piv);   // a single row, or a single column's one pivot
+        z.pr[z.np] = last;
+        z.pc[z.np] = z.rpm_col[last];
+        ++z.np;
+        add128(rows, last);
+        add128(cols, z.rpm_col[last]);
+        return;
+    }
+    const Set128 rt = lowest128(R, nr / 2), rb = minus128(R, rt);
+    const Set128 cl = lowest128(C, nc / 2), cr = minus128(C, cl);
+    Set128 pl;   // pivots of this call whose column lies in cl
+    for (int w = 0; w < 2; ++w)
+        for (uint64_t x = w ? piv.hi : piv.lo; x; x &= x - 1) {
+            const int i = 64 * w + __builtin_ctzll(x);
+            if (has128(cl, z.rpm_col[i])) add128(pl, i);
+        }
+    const Set128 pr = minus128(piv, pl);
+    Set128 r1, c1, r2, c2, r3, c3, r4, c4;
+    zorder_tile(z, rt, cl, pl, r1, c1);                                               // A1
+    zorder_tile(z, minus128(rt, r1), cr, pr, r2, c2);                                 // F
+    // the rows paired with a set of pivot columns are the rows emitted with them
+    zorder_tile(z, rb, minus128(cl, c1), minus128(pl, r1), r3, c3);                   // G
+    zorder_tile(z, minus128(rb, r3), minus128(cr, c2), minus128(pr, r2), r4, c4);     // R
+    rows = or128(or128(r1, r2), or128(r3, r4));
+    cols = or128(or128(c1, c2), or128(c3, c4));
+}
+
 void zorder_from_rpm(int64_t m, int64_t n, const int32_t *rpm_col_in, std::vector<int32_t> &prow,
                      std::vector<int32_t> &pcol) {
+    if (m <= 128 && n <= 128) {
+        ZTile z;
+        z.rpm_col = rpm_col_in;
+        Set128 R, C, pc;
+        for (int i = 0; i < m; ++i) {
+            add128(R, i);
+            if (rpm_col_in[i] >= 0 && rpm_col_in[i] < n) add128(pc, i);
+        }
+        for (int j = 0; j < n; ++j) add128(C, j);
+        Set128 rp, cp;
+        zorder_tile(z, R, C, pc, rp, cp);
+        prow.assign(z.pr, z.pr + z.np);
+        pcol.assign(z.pc, z.pc + z.np);
+        for (int i = 0; i < m; ++i)
+            if (!has128(rp, i)) prow.push_back(i);
+        for (int j = 0; j < n; ++j)
+            if (!has128(cp, j)) pcol.push_back(j);
+        return;
+    }
     std::vector<int32_t> rows((size_t)m), cols((size_t)n), rpm(rpm_col_in, rpm_col_in + m), colpos;
     std::iota(rows.begin(), rows.end(), 0);
     std::iota(cols.begin(), cols.end(), 0);
