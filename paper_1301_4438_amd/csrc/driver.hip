@@ -746,8 +746,10 @@ static void zorder_tile(ZTile &z, const Set128 &R, const Set128 &C, const Set128
     const Set128 piv = and128(R, pc);
     if (!piv.lo && !piv.hi) return;
     const int nr = count128(R), nc = count128(C);
-    if (nr == 1 || nc == 1) {
-        const int last = top128(piv);   // a single row, or a single column's one pivot
+    if (nr == 1 || nc == 1 || count128(piv) == 1) {
+        // a single row or column holds one pivot; a block with one pivot
+        // emits it wherever the splits put it
+        const int last = top128(piv);
         z.pr[z.np] = last;
         z.pc[z.np] = z.rpm_col[last];
         ++z.np;

@@ -97,6 +97,7 @@ __global__ __launch_bounds__(256) void build_inv_table_kernel(uint16_t *tab, Mod
 // attempt leaves the input untouched.
 
 typedef double bc_v4d __attribute__((ext_vector_type(4)));
+typedef double bc_v8d __attribute__((ext_vector_type(8)));
 
 // Value of x held by lane `src` (wave-uniform), for every lane.
 __device__ __forceinline__ double bc_lane(double x, int src) {
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
         }
         tab = (const uint16_t *)dyn;
     }
-    double v[R][R];
+    bc_v8d v[R];   // v[a][b]: entry (ty + 16 a, tx + 16 b)
 #pragma unroll
     for (int a = 0; a < R; ++a)
 #pragma unroll
@@ -579,9 +580,11 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
     uint32_t dead = 0;   // bit b: column tx + 16 b is a pivot column
     __syncthreads();
     int r = 0;
-    auto reduce_all = [&]() __attribute__((always_inline)) {
+    // symmetric reduction of register blocks a0 .. R-1 (the rows still open)
+    auto reduce_from = [&](auto A0) __attribute__((always_inline)) {
+        constexpr int a0 = decltype(A0)::value;
 #pragma unroll
-        for (int a = 0; a < R; ++a)
+        for (int a = a0; a < R; ++a)
 #pragma unroll
             for (int b = 0; b < R; ++b) v[a][b] = sym_reduce(v[a][b], mod);
     };
@@ -617,13 +620,12 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
         if (tx == sl) dead |= 1u << bj;
         // multipliers: column jc of rows ty + 16 a sits in lane grp + sl,
         // register v[a][bj]
+        // (register blocks a < ai hold rows above row i, finished: skipped)
+        const int bju = __builtin_amdgcn_readfirstlane(bj);
         double l[R];
 #pragma unroll
-        for (int a = 0; a < R; ++a) {
-            double sel = 0.0;
-#pragma unroll
-            for (int b = 0; b < R; ++b) sel = (b == bj) ? v[a][b] : sel;
-            const double c = __shfl(sel, grp + sl, 64);
+        for (int a = ai; a < R; ++a) {
+            const double c = __shfl(v[a][bju], grp + sl, 64);   // uniform index into the row's vector
             const int k = ty + 16 * a;
             l[a] = (k > i && k < m) ? sym_reduce(sym_reduce(c, mod) * inv, mod) : 0.0;
         }
@@ -631,10 +633,10 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
 #pragma unroll
         for (int b = 0; b < R; ++b) u[b] = Ub[buf][tx + 16 * b];
 #pragma unroll
-        for (int a = 0; a < R; ++a)
+        for (int a = ai; a < R; ++a)
 #pragma unroll
             for (int b = 0; b < R; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
-        if (RED1) reduce_all();
+        if (RED1) reduce_from(std::integral_constant<int, ai>{});
         // Ub and mins of this row are read again only by threads that have
         // not yet passed the next row's barrier; the row after next rewrites
         // them after that barrier.
@@ -643,7 +645,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
     {                                                                                             \
         const int ihi = (K) * 16 + 16 < m ? (K) * 16 + 16 : m;                                    \
         for (int i = (K) * 16; i < ihi; ++i) row_step(i, std::integral_constant<int, (K)>{});     \
-        if (!RED1) reduce_all();                                                                  \
+        if (!RED1) reduce_from(std::integral_constant<int, (K) + 1 < R ? (K) + 1 : R>{});        \
     }
     PLUQ_RPM_BLOCK(0)
     PLUQ_RPM_BLOCK(1)
