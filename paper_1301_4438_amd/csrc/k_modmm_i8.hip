@@ -19,22 +19,23 @@
 //   limb_split_kernel -- writes the digit planes of the operand blocks into
 //     workspace, [rows][Kp] int8 with the inner dimension contiguous (B is
 //     transposed on the way through LDS), zero-padded to a multiple of 64.
-//   modmm_i8_kernel   -- 128 x 128 output tile per work-group: for two
-//     digits 2 x 4 waves of 64 x 32 (2 x 1 blocks of v_mfma_i32_32x32x32_i8
-//     per limb product), for one digit 2 x 2 waves of 64 x 64; the planes are staged in LDS 64 bytes of K at a
-//     time (rows padded to 80 bytes so that the 16-byte fragment reads of a
-//     wave hit distinct banks), double-buffered: the next panel's global
-//     loads are issued before the current panel's matrix-core work and
-//     stored into the other buffer after it, so one barrier per panel
-//     suffices.  With the three limb sums of two digits a 64 x 64 wave tile
-//     would fill the AGPRs and leave one wave per SIMD; at 64 x 32 two
-//     waves share each SIMD and cover each other's load and barrier waits.
-//     One digit has a quarter of the matrix-core work per panel and keeps
-//     the larger wave tile for its operand reuse.  Tiles are
-//     handed out XCD by XCD: the work-groups that one XCD runs (hardware
-//     dispatch is round-robin over the 8 XCDs) take a contiguous range of
-//     tiles in an order grouped by 8 tile rows, so that the A and B panels
-//     they share stay in that XCD's L2.
+//   modmm_i8_kernel   -- four waves per work-group.  Two digits: a
+//     128 x 64 output tile, 2 x 2 waves of 64 x 32 (2 x 1 blocks of
+//     v_mfma_i32_32x32x32_i8 per limb product); with the three limb sums a
+//     wave holds about 150 registers, so three work-groups share a compute
+//     unit and, having barriers of their own, cover each other's load and
+//     barrier waits.  One digit: a 128 x 128 tile, 2 x 2 waves of 64 x 64
+//     (a quarter of the matrix-core work per panel; the larger wave tile
+//     keeps the operand reuse).  The planes are staged in LDS 64 bytes of K
+//     at a time (the four 16-byte chunks of a row permuted by an XOR of row
+//     bits, so that both the fragment reads and the stores of a wave hit
+//     distinct banks); with two digits the panels are double-buffered: the
+//     next panel's global loads are issued before the current panel's
+//     matrix-core work and stored into the other buffer after it, so one
+//     barrier per panel suffices.  Tiles are handed out XCD by XCD: the
+//     work-groups that one XCD runs (hardware dispatch is round-robin over
+//     the 8 XCDs) take a contiguous range of tiles in an order grouped by 8
+//     tile rows, so that the A and B panels they share stay in that XCD's L2.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -44,9 +45,12 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int I8_GROUP = 8;   // tile rows per group of the tile order
-// threads per 128 x 128 tile: 8 waves of 64 x 32 for two digits, 4 waves
-// of 64 x 64 for one
+// 4 waves per work-group: 128 x 64 tiles of 64 x 32 wave tiles for two
+// digits (three work-groups per compute unit), 128 x 128 tiles of 64 x 64
+// wave tiles for one (two per compute unit)
 __host__ __device__ constexpr int i8_threads(int nl) { return nl == 2 ? 512 : 256; }
+__host__ __device__ constexpr int i8_bn(int nl) { return nl == 2 ? 128 : 128; }
+__host__ __device__ constexpr int i8_blocks(int nl) { return nl == 2 ? 1 : 2; }
 
 // ------------------------------------------------------------------ split --
 
@@ -206,12 +210,22 @@ struct I8Args {
     ModP mod;
 };
 
+// Position of 16-byte chunk c of plane row `row` inside its 64-byte LDS row:
+// c ^ (2 b2 + (b1 ^ b3)) with b_k bit k of the row.  The fragment reads (8 or
+// 16 consecutive lanes on consecutive rows, one chunk) and the stores (2 or
+// 4 consecutive rows, all four chunks) then fall on distinct banks, whether
+// a 16-byte access is served 8 lanes at a time over 32 banks or 16 lanes at
+// a time over 64.
+__device__ __forceinline__ int i8_swz(int row, int c) {
+    return (c ^ (((row >> 1) ^ (row >> 3)) & 1) ^ (row & 4) >> 1) * 16;
+}
+
 template <typename T, int NL>
-__global__ __launch_bounds__(i8_threads(NL), 2) void modmm_i8_kernel(const I8Args g) {
-    constexpr int BM = 128, BN = 128, BK = 64, LDP = BK + 16;
+__global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel(const I8Args g) {
+    constexpr int BM = 128, BN = i8_bn(NL), BK = 64, LDP = BK;
     constexpr int NS = NL == 2 ? 3 : 1;   // limb sums S0 (, S1, S2)
     constexpr int JB = NL == 2 ? 1 : 2;   // 32-column blocks per wave
-    constexpr int NT = i8_threads(NL), WN = 4 / JB, RPT = BM / (NT / 4);
+    constexpr int NT = i8_threads(NL), WN = BN / (32 * JB), RPTA = BM / (NT / 4), RPTB = BN / (NT / 4);
     // two digits: double-buffered panels; one digit: a single buffer (two
     // barriers per panel), which keeps two work-groups per compute unit
     constexpr bool DB = NL == 2;
@@ -245,34 +259,39 @@ __global__ __launch_bounds__(i8_threads(NL), 2) void modmm_i8_kernel(const I8Arg
                 for (int v = 0; v < 16; ++v) acc[s][i][j][v] = 0;
 
     // Global loads: 16 bytes per thread, plane and row, plane rows
-    // tid/4 + r NT/4 (r < RPT), chunk tid%4.  Rows past M (N) are clamped
+    // tid/4 + r NT/4 (r < RPTA for A, RPTB for B), chunk tid%4.  Rows past M (N) are clamped
     // to the last valid row: their products only reach outputs that are
     // never stored.
     const int lr = tid >> 2, lc = (tid & 3) * 16;
-    int64_t ar[RPT], br[RPT];
+    int64_t ar[RPTA], br[RPTB];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        ar[r] = (int64_t)min(row0 + lr + r * (NT / 4), M - 1) * g.lda + lc;
-        br[r] = (int64_t)min(col0 + lr + r * (NT / 4), N - 1) * g.ldb + lc;
-    }
-    v4i pa[NL][RPT], pb[NL][RPT];
+    for (int r = 0; r < RPTA; ++r) ar[r] = (int64_t)min(row0 + lr + r * (NT / 4), M - 1) * g.lda + lc;
+#pragma unroll
+    for (int r = 0; r < RPTB; ++r) br[r] = (int64_t)min(col0 + lr + r * (NT / 4), N - 1) * g.ldb + lc;
+    v4i pa[NL][RPTA], pb[NL][RPTB];
     auto load = [&](int k0) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l)
+        for (int l = 0; l < NL; ++l) {
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                pa[l][r] = *(const v4i *)(g.a[l] + ar[r] + k0);
-                pb[l][r] = *(const v4i *)(g.b[l] + br[r] + k0);
-            }
+            for (int r = 0; r < RPTA; ++r) pa[l][r] = *(const v4i *)(g.a[l] + ar[r] + k0);
+#pragma unroll
+            for (int r = 0; r < RPTB; ++r) pb[l][r] = *(const v4i *)(g.b[l] + br[r] + k0);
+        }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l)
+        for (int l = 0; l < NL; ++l) {
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                *(v4i *)&As[buf][l][(lr + r * (NT / 4)) * LDP + lc] = pa[l][r];
-                *(v4i *)&Bs[buf][l][(lr + r * (NT / 4)) * LDP + lc] = pb[l][r];
+            for (int r = 0; r < RPTA; ++r) {
+                const int row = lr + r * (NT / 4);
+                *(v4i *)&As[buf][l][row * LDP + i8_swz(row, lc >> 4)] = pa[l][r];
             }
+#pragma unroll
+            for (int r = 0; r < RPTB; ++r) {
+                const int row = lr + r * (NT / 4);
+                *(v4i *)&Bs[buf][l][row * LDP + i8_swz(row, lc >> 4)] = pb[l][r];
+            }
+        }
     };
 
     const int steps = g.Kp / BK;
@@ -293,36 +312,52 @@ __global__ __launch_bounds__(i8_threads(NL), 2) void modmm_i8_kernel(const I8Arg
         // buffers it is stored into the other one, which every wave
         // finished reading before the barrier that ended the previous step
         if (s + 1 < steps) load((s + 1) * BK);
+        // All fragments of the panel are read before the first product
+        // (v_mfma_i32_32x32x32_i8: lane holds row (A) / column (B) lane%32
+        // and inner indices 16*(lane/32) .. +15 of a 32-deep step), so the
+        // LDS latency is paid once per panel rather than between products.
+        v4i fa[2][NL][2], fb[2][NL][JB];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            // v_mfma_i32_32x32x32_i8: lane holds row (A) / column (B) lane%32
-            // and inner indices 16*(lane/32) .. +15 of the 32-deep step.
-            const int ko = ks * 32 + (lane >> 5) * 16;
-            v4i fa[NL][2], fb[NL][JB];
+            const int kc = ks * 2 + (lane >> 5);   // 16-byte chunk of the 64-deep panel
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
-                    fa[l][i] = *(const v4i *)&As[buf][l][(wm0 + 32 * i + (lane & 31)) * LDP + ko];
-#pragma unroll
-                for (int j = 0; j < JB; ++j)
-                    fb[l][j] = *(const v4i *)&Bs[buf][l][(wn0 + 32 * j + (lane & 31)) * LDP + ko];
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < 2; ++i) {
+                    const int row = wm0 + 32 * i + (lane & 31);
+                    fa[ks][l][i] = *(const v4i *)&As[buf][l][row * LDP + i8_swz(row, kc)];
+                }
 #pragma unroll
                 for (int j = 0; j < JB; ++j) {
-                    acc[0][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[0][j], acc[0][i][j], 0, 0, 0);
-                    if (NL == 2) {
-                        acc[NS - 2][i][j] =
-                            __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[0][i], fb[NL - 1][j], acc[NS - 2][i][j], 0, 0, 0);
-                        acc[NS - 2][i][j] =
-                            __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[NL - 1][i], fb[0][j], acc[NS - 2][i][j], 0, 0, 0);
-                        acc[NS - 1][i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[NL - 1][i], fb[NL - 1][j],
-                                                                                   acc[NS - 1][i][j], 0, 0, 0);
-                    }
+                    const int row = wn0 + 32 * j + (lane & 31);
+                    fb[ks][l][j] = *(const v4i *)&Bs[buf][l][row * LDP + i8_swz(row, kc)];
                 }
+            }
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < JB; ++j) {
+                auto mfma = [&](int sidx, int i, int la, int lb) __attribute__((always_inline)) {
+                    acc[sidx][i][j] =
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks][la][i], fb[ks][lb][j], acc[sidx][i][j], 0, 0, 0);
+                };
+                if (NL == 2) {
+                    // the two products into S1 of a block are three products apart
+                    mfma(0, 0, 0, 0);
+                    mfma(NS - 2, 0, 0, NL - 1);
+                    mfma(0, 1, 0, 0);
+                    mfma(NS - 2, 1, 0, NL - 1);
+                    mfma(NS - 1, 0, NL - 1, NL - 1);
+                    mfma(NS - 2, 0, NL - 1, 0);
+                    mfma(NS - 1, 1, NL - 1, NL - 1);
+                    mfma(NS - 2, 1, NL - 1, 0);
+                } else {
+                    mfma(0, 0, 0, 0);
+                    mfma(0, 1, 0, 0);
+                }
+            }
         if (DB) {
             if (s + 1 < steps) stash(buf ^ 1);
             __syncthreads();
@@ -390,7 +425,7 @@ hipError_t launch_modmm_i8(int dtype, void *C, int64_t ldc, int M, int N, int Kp
     g.M = M;
     g.N = N;
     g.Kp = Kp;
-    g.tilesN = (int)cdiv64(N, 128);
+    g.tilesN = (int)cdiv64(N, i8_bn(nl));
     g.a[0] = a[0];
     g.a[1] = nl == 2 ? a[1] : a[0];
     g.b[0] = b[0];
