@@ -79,7 +79,13 @@ __global__ __launch_bounds__(NTH) void modmm_kernel(const MMArgs args) {
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int ELA = BM * BK / NTH;   // A elements loaded per thread and panel
     constexpr int ELB = BN * BK / NTH;   // B elements loaded per thread and panel
-    constexpr int PA = BK + 1, PB = BN + 1;
+    // LDS row strides (elements) that keep the fragment reads free of bank
+    // conflicts (32 banks of 4 bytes; a 64-lane read of 4-byte words is
+    // served 32 lanes at a time, of 8-byte words 16 at a time): float64
+    // needs an odd A stride, float32 an A stride of 2 and a B stride of 16
+    // modulo 32 (lanes 0-15 and 16-31 read two consecutive inner indices).
+    constexpr int PA = sizeof(CT) == 4 ? BK + 2 : BK + 1;
+    constexpr int PB = sizeof(CT) == 4 ? BN + 16 : BN + 1;
     constexpr int NB = DB ? 2 : 1;
     static_assert(FN >= 1 && ELA >= 1 && ELB >= 1 && ELA <= 32 && ELB <= 32, "tile shape");
     __shared__ CT As[NB][BM * PA];
