@@ -19,17 +19,17 @@
 //   limb_split_kernel -- writes the digit planes of the operand blocks into
 //     workspace, [rows][Kp] int8 with the inner dimension contiguous (B is
 //     transposed on the way through LDS), zero-padded to a multiple of 64.
-//   modmm_i8_kernel   -- four waves per work-group.  Two digits: a
-//     128 x 64 output tile, 2 x 2 waves of 64 x 32 (2 x 1 blocks of
-//     v_mfma_i32_32x32x32_i8 per limb product); with the three limb sums a
-//     wave holds about 150 registers, so three work-groups share a compute
-//     unit and, having barriers of their own, cover each other's load and
-//     barrier waits.  One digit: a 128 x 128 tile, 2 x 2 waves of 64 x 64
-//     (a quarter of the matrix-core work per panel; the larger wave tile
-//     keeps the operand reuse).  The planes are staged in LDS 64 bytes of K
-//     at a time (the four 16-byte chunks of a row permuted by an XOR of row
-//     bits, so that both the fragment reads and the stores of a wave hit
-//     distinct banks); with two digits the panels are double-buffered: the
+//   modmm_i8_kernel   -- 128 x 128 output tile per work-group: for two
+//     digits 2 x 4 waves of 64 x 32 (2 x 1 blocks of v_mfma_i32_32x32x32_i8
+//     per limb product; with the three limb sums a 64 x 64 wave tile would
+//     leave one wave per SIMD), for one digit 2 x 2 waves of 64 x 64.
+//     Updates with fewer than 1024 such tiles take 64 x 64 tiles of 2 x 2
+//     waves of 32 x 32 instead, so that they still spread over the compute
+//     units.  The planes are staged in LDS 64 bytes of K at a time (the four
+//     16-byte chunks of a row permuted by an XOR of row bits, so that both
+//     the fragment reads and the stores of a wave hit distinct banks); a
+//     wave reads all fragments of a panel before its products.  With two
+//     digits (and on the small tile) the panels are double-buffered: the
 //     next panel's global loads are issued before the current panel's
 //     matrix-core work and stored into the other buffer after it, so one
 //     barrier per panel suffices.  Tiles are handed out XCD by XCD: the
@@ -45,12 +45,14 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int I8_GROUP = 8;   // tile rows per group of the tile order
-// 4 waves per work-group: 128 x 64 tiles of 64 x 32 wave tiles for two
-// digits (three work-groups per compute unit), 128 x 128 tiles of 64 x 64
-// wave tiles for one (two per compute unit)
-__host__ __device__ constexpr int i8_threads(int nl) { return nl == 2 ? 512 : 256; }
-__host__ __device__ constexpr int i8_bn(int nl) { return nl == 2 ? 128 : 128; }
-__host__ __device__ constexpr int i8_blocks(int nl) { return nl == 2 ? 1 : 2; }
+// Tile shapes.  Large: 128 x 128, 8 waves of 64 x 32 (two digits) or 4 waves
+// of 64 x 64 (one digit).  Small (SM): 64 x 64, 4 waves of 32 x 32, for
+// updates whose 128 x 128 tiles would not fill the compute units.
+__host__ __device__ constexpr int i8_tile(bool sm) { return sm ? 64 : 128; }
+__host__ __device__ constexpr int i8_threads(int nl, bool sm) { return (nl == 2 && !sm) ? 512 : 256; }
+__host__ __device__ constexpr int i8_blocks(int nl, bool sm) { return sm ? 2 : (nl == 2 ? 1 : 2); }
+// below this many 128 x 128 tiles an update takes the 64 x 64 tiles
+constexpr int64_t I8_SMALL_TILES = 1024;
 
 // ------------------------------------------------------------------ split --
 
@@ -220,15 +222,17 @@ __device__ __forceinline__ int i8_swz(int row, int c) {
     return (c ^ (((row >> 1) ^ (row >> 3)) & 1) ^ (row & 4) >> 1) * 16;
 }
 
-template <typename T, int NL>
-__global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel(const I8Args g) {
-    constexpr int BM = 128, BN = i8_bn(NL), BK = 64, LDP = BK;
-    constexpr int NS = NL == 2 ? 3 : 1;   // limb sums S0 (, S1, S2)
-    constexpr int JB = NL == 2 ? 1 : 2;   // 32-column blocks per wave
-    constexpr int NT = i8_threads(NL), WN = BN / (32 * JB), RPTA = BM / (NT / 4), RPTB = BN / (NT / 4);
-    // two digits: double-buffered panels; one digit: a single buffer (two
-    // barriers per panel), which keeps two work-groups per compute unit
-    constexpr bool DB = NL == 2;
+template <typename T, int NL, bool SM>
+__global__ __launch_bounds__(i8_threads(NL, SM), i8_blocks(NL, SM)) void modmm_i8_kernel(const I8Args g) {
+    constexpr int BM = i8_tile(SM), BN = i8_tile(SM), BK = 64, LDP = BK;
+    constexpr int NS = NL == 2 ? 3 : 1;                // limb sums S0 (, S1, S2)
+    constexpr int IB = SM ? 1 : 2;                     // 32-row blocks per wave
+    constexpr int JB = (SM || NL == 2) ? 1 : 2;        // 32-column blocks per wave
+    constexpr int NT = i8_threads(NL, SM), WN = BN / (32 * JB), RPTA = BM / (NT / 4), RPTB = BN / (NT / 4);
+    // double-buffered panels for two digits and for the small tile; one
+    // digit on the large tile keeps a single buffer (two barriers per
+    // panel), which keeps two work-groups per compute unit
+    constexpr bool DB = NL == 2 || SM;
     constexpr int NB = DB ? 2 : 1;
     __shared__ __attribute__((aligned(16))) int8_t As[NB][NL][BM * LDP];
     __shared__ __attribute__((aligned(16))) int8_t Bs[NB][NL][BN * LDP];
@@ -246,13 +250,13 @@ __global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel
     const int row0 = tr * BM, col0 = tc * BN;
     const int M = g.M, N = g.N;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm0 = (wave / WN) * 64, wn0 = (wave % WN) * 32 * JB;
+    const int wm0 = (wave / WN) * 32 * IB, wn0 = (wave % WN) * 32 * JB;
 
-    v16i acc[NS][2][JB];
+    v16i acc[NS][IB][JB];
 #pragma unroll
     for (int s = 0; s < NS; ++s)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < IB; ++i)
 #pragma unroll
             for (int j = 0; j < JB; ++j)
 #pragma unroll
@@ -316,14 +320,14 @@ __global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel
         // (v_mfma_i32_32x32x32_i8: lane holds row (A) / column (B) lane%32
         // and inner indices 16*(lane/32) .. +15 of a 32-deep step), so the
         // LDS latency is paid once per panel rather than between products.
-        v4i fa[2][NL][2], fb[2][NL][JB];
+        v4i fa[2][NL][IB], fb[2][NL][JB];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
             const int kc = ks * 2 + (lane >> 5);   // 16-byte chunk of the 64-deep panel
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
+                for (int i = 0; i < IB; ++i) {
                     const int row = wm0 + 32 * i + (lane & 31);
                     fa[ks][l][i] = *(const v4i *)&As[buf][l][row * LDP + i8_swz(row, kc)];
                 }
@@ -344,18 +348,21 @@ __global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel
                         __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[ks][la][i], fb[ks][lb][j], acc[sidx][i][j], 0, 0, 0);
                 };
                 if (NL == 2) {
-                    // the two products into S1 of a block are three products apart
-                    mfma(0, 0, 0, 0);
-                    mfma(NS - 2, 0, 0, NL - 1);
-                    mfma(0, 1, 0, 0);
-                    mfma(NS - 2, 1, 0, NL - 1);
-                    mfma(NS - 1, 0, NL - 1, NL - 1);
-                    mfma(NS - 2, 0, NL - 1, 0);
-                    mfma(NS - 1, 1, NL - 1, NL - 1);
-                    mfma(NS - 2, 1, NL - 1, 0);
+                    // the two products into S1 of a block are IB + 1
+                    // products apart
+#pragma unroll
+                    for (int i = 0; i < IB; ++i) {
+                        mfma(0, i, 0, 0);
+                        mfma(NS - 2, i, 0, NL - 1);
+                    }
+#pragma unroll
+                    for (int i = 0; i < IB; ++i) {
+                        mfma(NS - 1, i, NL - 1, NL - 1);
+                        mfma(NS - 2, i, NL - 1, 0);
+                    }
                 } else {
-                    mfma(0, 0, 0, 0);
-                    mfma(0, 1, 0, 0);
+#pragma unroll
+                    for (int i = 0; i < IB; ++i) mfma(0, i, 0, 0);
                 }
             }
         if (DB) {
@@ -374,7 +381,7 @@ __global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel
 #pragma unroll
     for (int j = 0; j < JB; ++j)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < IB; ++i) {
             const int gc = col0 + wn0 + 32 * j + (lane & 31);
             double cv[16];
 #pragma unroll
@@ -397,18 +404,18 @@ __global__ __launch_bounds__(i8_threads(NL), i8_blocks(NL)) void modmm_i8_kernel
     if (nz && g.nzflag) *g.nzflag = g.nzgen;
 }
 
-template <typename T, int NL>
+template <typename T, int NL, bool SM>
 static hipError_t i8_t(I8Args &a, int total, hipStream_t st) {
-    PLUQ_LAUNCH((modmm_i8_kernel<T, NL>), dim3(total), dim3(i8_threads(NL)), 0, st, a);
+    PLUQ_LAUNCH((modmm_i8_kernel<T, NL, SM>), dim3(total), dim3(i8_threads(NL, SM)), 0, st, a);
     return hipGetLastError();
 }
 
-template <int NL>
+template <int NL, bool SM>
 static hipError_t i8_dt(int dtype, I8Args &a, int total, hipStream_t st) {
     switch (dtype) {
-    case DT_I64: return i8_t<int64_t, NL>(a, total, st);
-    case DT_F64: return i8_t<double, NL>(a, total, st);
-    case DT_I32: return i8_t<int32_t, NL>(a, total, st);
+    case DT_I64: return i8_t<int64_t, NL, SM>(a, total, st);
+    case DT_F64: return i8_t<double, NL, SM>(a, total, st);
+    case DT_I32: return i8_t<int32_t, NL, SM>(a, total, st);
     }
     return hipErrorInvalidValue;
 }
@@ -425,7 +432,9 @@ hipError_t launch_modmm_i8(int dtype, void *C, int64_t ldc, int M, int N, int Kp
     g.M = M;
     g.N = N;
     g.Kp = Kp;
-    g.tilesN = (int)cdiv64(N, i8_bn(nl));
+    const bool sm = cdiv64(M, 128) * cdiv64(N, 128) < I8_SMALL_TILES;
+    const int tile = sm ? i8_tile(true) : i8_tile(false);
+    g.tilesN = (int)cdiv64(N, tile);
     g.a[0] = a[0];
     g.a[1] = nl == 2 ? a[1] : a[0];
     g.b[0] = b[0];
@@ -437,8 +446,9 @@ hipError_t launch_modmm_i8(int dtype, void *C, int64_t ldc, int M, int N, int Kp
     g.mod.p = p;
     g.mod.pinv = 1.0 / p;
     g.mod.half = (double)((int64_t)p / 2);
-    const int total = (int)(cdiv64(M, 128) * g.tilesN);
-    return nl == 1 ? i8_dt<1>(dtype, g, total, st) : i8_dt<2>(dtype, g, total, st);
+    const int total = (int)(cdiv64(M, tile) * g.tilesN);
+    if (sm) return nl == 1 ? i8_dt<1, true>(dtype, g, total, st) : i8_dt<2, true>(dtype, g, total, st);
+    return nl == 1 ? i8_dt<1, false>(dtype, g, total, st) : i8_dt<2, false>(dtype, g, total, st);
 }
 
 }  // namespace pluq

@@ -67,6 +67,22 @@ def test_modmm_int8_parity(gpu_lib, dtype, p):
         assert np.array_equal(_np(Cd), oracle.mm(C, A, B, p)), (m, n, k)
 
 
+@pytest.mark.parametrize("p", [251, 65521])
+def test_modmm_int8_tile_shapes(gpu_lib, p):
+    """Both tile shapes of the int8 GEMM on ragged edges: 4100 x 4097 has
+    33 x 33 = 1089 tiles of 128 x 128 (the large tile), 4096 x 3968 has
+    32 x 31 = 992 (below 1024: the 64 x 64 tile)."""
+    import torch
+    g = np.random.default_rng(3000 + p)
+    for (m, n, k) in [(4100, 4097, 100), (4096, 3968, 70)]:
+        note("modmm int8 tile shape", p, m, n, k)
+        C = g.integers(0, p, (m, n)); A = g.integers(0, p, (m, k)); B = g.integers(0, p, (k, n))
+        Cd, Ad, Bd = _dev(C, "float64"), _dev(A, "float64"), _dev(B, "float64")
+        gpu_lib.pluq_modmm(Cd, Ad, Bd, p, form="int8")
+        torch.cuda.synchronize()
+        assert np.array_equal(_np(Cd), oracle.mm(C, A, B, p)), (m, n, k)
+
+
 def test_modmm_int8_all_max(gpu_lib):
     """Every operand p-1 with the largest one-launch depth: the largest
     limb sums the int32 accumulators can see for these shapes."""
