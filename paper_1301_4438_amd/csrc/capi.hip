@@ -606,6 +606,7 @@ pluq_status pluq_modp(int64_t m, int64_t n, void *dA, int64_t lda, pluq_dtype dt
             // with the last read-back: the base cases' error flag
             c.read_status(STAT_ERR, 1);
             c.check_err();
+            c.sync();   // the stream is idle on return
         } else if (m > 0 || n > 0) {
             c.sync();
         }

@@ -20,6 +20,7 @@
 // host (they are index bookkeeping) and uploaded only when a permutation is
 // not the identity.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <exception>
 #include <numeric>
@@ -131,13 +132,41 @@ int32_t Ctx::next_gen() {
     return g_gen;
 }
 
-// Read `count` int32 status words back (synchronising).  When the kernels
-// write them into mapped host memory the synchronisation alone suffices.
+// Completion marker: written after every earlier command of the stream has
+// finished (stream order), so the host that sees it sees their results too.
+__global__ void mark_kernel(int32_t *w, int32_t gen) {
+    if (threadIdx.x == 0) *(volatile int32_t *)w = gen;
+}
+
+// Read `count` int32 status words back.  When the kernels write them into
+// mapped host memory, a one-thread marker kernel follows them on the stream
+// and the host waits for its generation in that memory, which ends sooner
+// than a stream synchronisation; past a bounded wait (a device that stopped
+// making progress, or a failed launch) it synchronises, which also reports
+// any error.  Otherwise the words are copied back and the stream is
+// synchronised.
 void Ctx::read_status(int64_t offset, int64_t count) {
-    if (!stat_mapped)
+    if (!stat_mapped) {
         check(hipMemcpyAsync(h_stat + offset, d_stat + offset, (size_t)count * sizeof(int32_t),
                              hipMemcpyDeviceToHost, st));
-    sync();
+        sync();
+        return;
+    }
+    const int32_t gen = next_gen();
+    hipLaunchKernelGGL(mark_kernel, dim3(1), dim3(64), 0, st, d_stat + STAT_MARK, gen);
+    check(hipGetLastError());
+    const int32_t *h = h_stat + STAT_MARK;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int spin = 0; __atomic_load_n(h, __ATOMIC_ACQUIRE) != gen; ++spin) {
+        __builtin_ia32_pause();
+        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
+            sync();
+            if (__atomic_load_n(h, __ATOMIC_ACQUIRE) != gen) throw DeviceError{hipErrorUnknown};
+            return;
+        }
+    }
+    idx_used = 0;
+    stats.syncs++;
 }
 
 // ------------------------------------------------------------ permutations --

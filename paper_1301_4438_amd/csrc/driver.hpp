@@ -87,6 +87,7 @@ struct PermJob {
 constexpr int64_t STAT_FLAG = 0;     // 8 zero-flag slots
 constexpr int64_t STAT_SPEC = 8;     // sticky flag: a speculated base case failed
 constexpr int64_t STAT_ERR = 9;      // sticky flag: an ordered base case failed its self-check
+constexpr int64_t STAT_MARK = 10;    // completion marker of a read-back (generation)
 constexpr int64_t STAT_BC = 64;      // base-case status: r, ok / rpm columns
 constexpr int64_t STAT_WORDS = 64 + 2 + 16384 + 64;
 
