@@ -529,13 +529,17 @@ __global__ __launch_bounds__(TILE * 4) void bc_lu_kernel(T *A, int64_t lda, int 
 // first non-zero column; after the barrier every thread finds the pivot
 // column, reads the pivot and its inverse (LDS table when p <= 65536) itself,
 // fetches column jc of its own rows from the lane of its 16-lane group that
-// holds it (a within-wave shuffle), forms its multipliers, and applies the
-// row to its 8 x 8 entries with branch-free multiply-adds (multipliers of
-// rows <= i and published values of dead columns are 0).  Row i's values and
-// first-column words are double-buffered by row parity, so the next row's
-// owners can publish while the others still read.  The tile is reduced
+// holds it (a within-wave shuffle of the register selected by the uniform
+// index jc / 16), forms its multipliers, and applies the row with
+// branch-free multiply-adds to its register rows of the current and later
+// 16-row blocks (earlier blocks are finished; multipliers of rows <= i and
+// published values of dead columns are 0).  Row i's values and first-column
+// words are double-buffered by row parity, so the next row's owners can
+// publish while the others still read.  The open rows are reduced
 // (symmetric reduction) after every block of 16 rows, or after every pivot
-// when RED1 (p close to 2^25).
+// when RED1 (p close to 2^25).  Each row costs about 700 cycles of
+// dependent latency (three LDS round trips, the barrier, the multiplier
+// chain), not arithmetic.
 template <typename T, bool RED1>
 __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t lda, int m, int n, ModP mod,
                                                             const uint16_t *gtab, int32_t *status) {
