@@ -21,15 +21,14 @@ namespace pluq {
 // lower-triangular scheme on X = L^{-1} split into 4 x 4 blocks of 16:
 //   the four diagonal blocks D_k = L_kk^{-1} by forward substitution (one
 //   wave each, a lane per column, the diagonal inverses computed first);
-//   then the blocks below, by distance d = i - j = 1, 2, 3, all entries of a
-//   distance at once:  T = sum_{k=j}^{i-1} L_ik X_kj,  X_ij = -D_i T.
+//   then the blocks below, by distance d = i - j = 1, 2, 3, one wave per
+//   block of a distance on the float64 matrix cores:
+//   T = sum_{k=j}^{i-1} L_ik X_kj,  X_ij = -D_i T.
 // Products are of symmetric residues, reduced (symmetric reduction) after
-// every 16 terms; the sums run as two independent chains and the blocks of
-// one distance together, since the kernel is bound by dependent latency.
+// every 16 terms.
 struct DiagSmem {
     double Ls[64][65];   // strict lower part (symmetric residues)
     double Xs[64][65];   // the inverse being built (symmetric)
-    double Ts[3][16][17];
     double dinv[64];
 };
 
@@ -40,7 +39,6 @@ __device__ __forceinline__ void diag_inv_body(const T *Tm, int64_t ldt, int r, T
                                               DiagSmem &sm) {
     auto &Ls = sm.Ls;
     auto &Xs = sm.Xs;
-    auto &Ts = sm.Ts;
     auto &dinv = sm.dinv;
     const int tid = threadIdx.x;
     const int o = blk * 64;
@@ -89,46 +87,45 @@ __device__ __forceinline__ void diag_inv_body(const T *Tm, int64_t ldt, int r, T
         }
     }
     __syncthreads();
-    const int a = tid >> 4, c = tid & 15;
-    // Off-diagonal 16 x 16 blocks by distance d = i - j; the blocks of one
-    // distance are independent and computed together (unrolled).
+    // Off-diagonal 16 x 16 blocks by distance d = i - j: wave w computes the
+    // block (w + d, w) when w < 4 - d, on the float64 matrix cores
+    // (v_mfma_f64_16x16x4f64: A operand row lane % 16, inner index
+    // lane / 16 + 4 kk; B operand inner index lane / 16 + 4 kk, column
+    // lane % 16; accumulator element v at row lane / 16 + 4 v, column
+    // lane % 16).  T = sum_k L_ik X_kj takes four products per k block (16
+    // terms below 2^52, reduced per block); X_ij = -D_i T then takes T's
+    // accumulator elements directly as its B operand (element kk holds rows
+    // 4 kk + lane / 16, the rows step kk needs).
+    {
+        typedef double v4d __attribute__((ext_vector_type(4)));
+        const int r16 = lane & 15, k4 = lane >> 4;
 #pragma unroll
-    for (int d = 1; d < 4; ++d) {
-        double acc[3];
+        for (int d = 1; d < 4; ++d) {
+            if (wv < 4 - d) {
+                const int j = wv, i = wv + d;
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
+                for (int k = j; k < i; ++k) {
+                    v4d part = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 4 - d; ++b) {
-            const int j = b, i = b + d;
-            double sb = 0.0;
+                    for (int kk = 0; kk < 4; ++kk)
+                        part = __builtin_amdgcn_mfma_f64_16x16x4f64(Ls[16 * i + r16][16 * k + 4 * kk + k4],
+                                                                     Xs[16 * k + 4 * kk + k4][16 * j + r16], part, 0,
+                                                                     0, 0);
 #pragma unroll
-            for (int k = j; k < i; ++k) {
-                // 16 products of symmetric residues (each below 2^48), reduced
-                double t0 = 0.0, t1 = 0.0;
-#pragma unroll
-                for (int q = 0; q < 16; q += 2) {
-                    t0 = fma(Ls[16 * i + a][16 * k + q], Xs[16 * k + q][16 * j + c], t0);
-                    t1 = fma(Ls[16 * i + a][16 * k + q + 1], Xs[16 * k + q + 1][16 * j + c], t1);
+                    for (int v = 0; v < 4; ++v) acc[v] += sym_reduce(part[v], mod);
                 }
-                sb += sym_reduce(t0 + t1, mod);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = sym_reduce(acc[v], mod);
+                v4d x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[16 * i + r16][16 * i + 4 * kk + k4], acc[kk], x, 0, 0,
+                                                             0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Xs[16 * i + k4 + 4 * v][16 * j + r16] = sym_reduce(-x[v], mod);
             }
-            acc[b] = sb;
+            __syncthreads();
         }
-#pragma unroll
-        for (int b = 0; b < 4 - d; ++b) Ts[b][a][c] = sym_reduce(acc[b], mod);
-        __syncthreads();
-#pragma unroll
-        for (int b = 0; b < 4 - d; ++b) {
-            const int i = b + d;
-            double t0 = 0.0, t1 = 0.0;
-#pragma unroll
-            for (int q = 0; q < 16; q += 2) {
-                t0 = fma(Xs[16 * i + a][16 * i + q], Ts[b][q][c], t0);
-                t1 = fma(Xs[16 * i + a][16 * i + q + 1], Ts[b][q + 1][c], t1);
-            }
-            acc[b] = t0 + t1;
-        }
-#pragma unroll
-        for (int b = 0; b < 4 - d; ++b) Xs[16 * (b + d) + a][16 * b + c] = sym_reduce(-acc[b], mod);
-        __syncthreads();
     }
     T *Wq = W + (int64_t)blk * 64 * 64;
 #pragma unroll
