@@ -23,6 +23,7 @@ small matrices as a replayed HIP graph against per-matrix launches
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c2]
                        [--no-cpu-baseline] [--no-comparisons]
+       python bench.py --only-mm | --only-batched   (one comparison alone, for profiling)
 """
 from __future__ import annotations
 
@@ -412,6 +413,8 @@ def main():
                     help="skip the other forms and workloads measured after the timed region")
     ap.add_argument("--only-mm", action="store_true",
                     help="time only the 8192 x 8192 x 4096 update in every form (for counter runs)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="time only the batch of 4096 matrices, batched and per matrix (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this library runs on one GPU; --gpus must be 1 (no multi-GPU path is built)",
@@ -422,6 +425,9 @@ def main():
     pl.load()
     if args.only_mm:
         print(json.dumps({"mm_8192x8192x4096": large_update(pl, args.seed)}), flush=True)
+        return
+    if args.only_batched:
+        print(json.dumps({"c5_batch4096_p65521": c5_batch(pl, args.seed)}), flush=True)
         return
     if args.workload == "c2":
         print(json.dumps(c2_pair(pl, args.seed)), flush=True)
