@@ -537,10 +537,12 @@ __global__ __launch_bounds__(TILE * 4) void bc_lu_kernel(T *A, int64_t lda, int 
 // words are double-buffered by row parity, so the next row's owners can
 // publish while the others still read.  The open rows are reduced
 // (symmetric reduction) after every block of 16 rows, or after every pivot
-// when RED1 (p close to 2^25).  Each row costs about 700 cycles of
-// dependent latency (three LDS round trips, the barrier, the multiplier
-// chain), not arithmetic.
-template <typename T, bool RED1>
+// when RED1 (p close to 2^25).  A pivot row costs dependent latency more
+// than arithmetic (the barrier, the first-column words, then the pivot and
+// its inverse from LDS with the column shuffles issued in between, the
+// multiplier chain), so the table is a compile-time choice (no branch
+// between those steps) and the status store comes after the update.
+template <typename T, bool RED1, bool TAB>
 __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t lda, int m, int n, ModP mod,
                                                             const uint16_t *gtab, int32_t *status) {
     constexpr int R = 8;
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
     const int tid = threadIdx.x;
     const int ty = tid >> 4, tx = tid & 15;
     const uint16_t *tab = nullptr;
-    if (gtab) {
+    if (TAB) {
         const int words = ((int)mod.p + 7) / 8;
         const uint4 *src = (const uint4 *)gtab;
         uint4 *dst = (uint4 *)dyn;
@@ -618,20 +620,24 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
         ++r;
         const int bj = jc >> 4, sl = jc & 15;
         double pv = Ub[buf][jc];
-        if (pv < 0.0) pv += mod.p;   // canonical, for the inverse
-        const double inv = tab ? (double)tab[(int)pv] : mod_inv(pv, mod);
-        if (tid == 0) status[1 + i] = jc;
-        if (tx == sl) dead |= 1u << bj;
-        // multipliers: column jc of rows ty + 16 a sits in lane grp + sl,
-        // register v[a][bj]
+        // column jc of rows ty + 16 a sits in lane grp + sl, register
+        // v[a][bj]: fetched while the pivot and its inverse are read
         // (register blocks a < ai hold rows above row i, finished: skipped)
         const int bju = __builtin_amdgcn_readfirstlane(bj);
+        double cs[R];
+#pragma unroll
+        for (int a = ai; a < R; ++a) cs[a] = __shfl(v[a][bju], grp + sl, 64);   // uniform index into the row's vector
+        if (pv < 0.0) pv += mod.p;   // canonical, for the inverse
+        double inv;
+        if constexpr (TAB) inv = (double)tab[(int)pv];
+        else inv = mod_inv(pv, mod);
+        if (tx == sl) dead |= 1u << bj;
         double l[R];
 #pragma unroll
         for (int a = ai; a < R; ++a) {
-            const double c = __shfl(v[a][bju], grp + sl, 64);   // uniform index into the row's vector
             const int k = ty + 16 * a;
-            l[a] = (k > i && k < m) ? sym_reduce(sym_reduce(c, mod) * inv, mod) : 0.0;
+            const double lv = sym_reduce(sym_reduce(cs[a], mod) * inv, mod);   // formed for every row: no branch
+            l[a] = (k > i && k < m) ? lv : 0.0;
         }
         double u[R];
 #pragma unroll
@@ -641,6 +647,7 @@ __global__ __launch_bounds__(BC_THREADS) void bc_rpm_kernel(const T *A, int64_t 
 #pragma unroll
             for (int b = 0; b < R; ++b) v[a][b] = fma(-l[a], u[b], v[a][b]);
         if (RED1) reduce_from(std::integral_constant<int, ai>{});
+        if (tid == 0) status[1 + i] = jc;
         // Ub and mins of this row are read again only by threads that have
         // not yet passed the next row's barrier; the row after next rewrites
         // them after that barrier.
@@ -691,12 +698,9 @@ hipError_t bc_init() {
     PLUQ_SETLDS((bc_lu_kernel<int64_t, 128, true>))
     PLUQ_SETLDS((bc_lu_kernel<double, 128, true>))
     PLUQ_SETLDS((bc_lu_kernel<int32_t, 128, true>))
-    PLUQ_SETLDS((bc_rpm_kernel<int64_t, false>))
-    PLUQ_SETLDS((bc_rpm_kernel<double, false>))
-    PLUQ_SETLDS((bc_rpm_kernel<int32_t, false>))
-    PLUQ_SETLDS((bc_rpm_kernel<int64_t, true>))
-    PLUQ_SETLDS((bc_rpm_kernel<double, true>))
-    PLUQ_SETLDS((bc_rpm_kernel<int32_t, true>))
+    PLUQ_SETLDS((bc_rpm_kernel<int64_t, false, true>))
+    PLUQ_SETLDS((bc_rpm_kernel<double, false, true>))
+    PLUQ_SETLDS((bc_rpm_kernel<int32_t, false, true>))
 #undef PLUQ_SETLDS
     hipError_t e = hipSuccess;
 #define PLUQ_SETOUT(K)                                                                                 \
@@ -785,13 +789,17 @@ hipError_t launch_bc_rpm(int dtype, const void *A, int64_t lda, int m, int n, do
     const bool red1 = (4503599627370496.0 - 2.0 * p) / (h * h) < 16.0;
     const size_t lds = tab ? BC_TAB_BYTES : 0;
     const ModP md = make_mod(p);
+    // red1 implies p > 65536: no table
 #define PLUQ_RPM(TT)                                                                                     \
     if (red1)                                                                                            \
-        PLUQ_LAUNCH((bc_rpm_kernel<TT, true>), dim3(1), dim3(BC_THREADS), lds, st, (const TT *)A, lda, m, n, md, \
-                    tab, status);                                                                        \
+        PLUQ_LAUNCH((bc_rpm_kernel<TT, true, false>), dim3(1), dim3(BC_THREADS), 0, st, (const TT *)A, lda, m, n, \
+                    md, nullptr, status);                                                                \
+    else if (tab)                                                                                        \
+        PLUQ_LAUNCH((bc_rpm_kernel<TT, false, true>), dim3(1), dim3(BC_THREADS), lds, st, (const TT *)A, lda, m, \
+                    n, md, tab, status);                                                                 \
     else                                                                                                 \
-        PLUQ_LAUNCH((bc_rpm_kernel<TT, false>), dim3(1), dim3(BC_THREADS), lds, st, (const TT *)A, lda, m, n, md, \
-                    tab, status);
+        PLUQ_LAUNCH((bc_rpm_kernel<TT, false, false>), dim3(1), dim3(BC_THREADS), 0, st, (const TT *)A, lda, m, \
+                    n, md, nullptr, status);
     switch (dtype) {
     case DT_I64: PLUQ_RPM(int64_t) break;
     case DT_F64: PLUQ_RPM(double) break;
